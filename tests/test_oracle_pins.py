@@ -1,0 +1,499 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and the mathematics.
+
+Each test checks the oracle against something other than itself: brute-force
+DFTs, finite-difference stencils built with np.roll, Kronecker-sum matrices,
+dense matrix exponentials / eigendecompositions / Schur forms, separable 1D
+eigenproblems, closed forms and the projector identities stated beside Fig. 1.
+A plausible slip in the oracle (a dropped 1/N^3, a wrong sign of k, a halved
+Laplacian, a transposed axis, a missing V in the step) fails at least one.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import oracle as O
+import synthetic as S
+
+
+def rnd(shape, seed):
+    g = np.random.default_rng(seed)
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+def kron_sum(M):
+    n = M.shape[0]
+    I = np.eye(n)
+    return np.kron(np.kron(M, I), I) + np.kron(np.kron(I, M), I) + np.kron(np.kron(I, I), M)
+
+
+def d2_periodic(n):
+    D = -2.0 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
+    D[0, -1] += 1.0
+    D[-1, 0] += 1.0
+    return D
+
+
+def d2_dirichlet(n):
+    return -2.0 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
+
+
+def paper_momenta(n):
+    """k in {-pi + 2pi/N, ..., 0, ..., pi} in natural order (Sec. 2)."""
+    return 2.0 * np.pi * np.arange(-n // 2 + 1, n // 2 + 1) / n
+
+
+def symbol_matrix_1d(n, t_of_k):
+    """D[x, y] = (1/N) sum_k t(k) exp(i k (x - y)) by explicit sums (no FFT)."""
+    ks = paper_momenta(n)
+    x = np.arange(n)
+    ph = np.exp(1j * np.outer(x, ks))
+    return (ph * t_of_k(ks)[None, :]) @ ph.conj().T / n
+
+
+def roll_laplacian_periodic(psi):
+    out = -6.0 * psi
+    for ax in range(3):
+        out = out + np.roll(psi, 1, axis=ax) + np.roll(psi, -1, axis=ax)
+    return out
+
+
+# ---------------------------------------------------------------- transforms
+
+@pytest.mark.parametrize("N", [6, 8, 10])
+def test_fft3_is_unnormalised_forward_dft(N):
+    psi = rnd((N, N, N), 1)
+    x = np.arange(N)
+    W = np.exp(-2j * np.pi * np.outer(x, x) / N)       # brute-force DFT matrix
+    ref = np.einsum("ai,bj,ck,ijk->abc", W, W, W, psi)
+    np.testing.assert_allclose(O.fft3(psi), ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+    np.testing.assert_allclose(O.ifft3(ref), psi, rtol=0, atol=1e-12 * np.abs(psi).max())
+
+
+def test_lattice_momenta_are_the_printed_set():
+    for N in (8, 10, 32):
+        k = O.lattice_momenta(N)
+        assert sorted(np.round(k, 14)) == sorted(np.round(paper_momenta(N), 14))
+        assert np.isclose(k.max(), np.pi) and k.min() > -np.pi + 1e-12
+
+
+# ------------------------------------------------------------ kinetic terms
+
+@pytest.mark.parametrize("N", [10, 12])
+def test_hk2_equals_periodic_seven_point_stencil(N):
+    a, m = 0.3, 1.7
+    psi = rnd((N, N, N), 2)
+    got = O.apply_kinetic(psi, O.K_NR_SIN2, a, m)
+    ref = -roll_laplacian_periodic(psi) / (2 * m * a * a)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_hk1_is_the_continuum_second_derivative_on_band_limited_modes():
+    N, a, m = 12, 0.4, 0.9
+    L = N * a
+    x = O.coords(N, a)
+    X1, X2, X3 = np.meshgrid(x, x, x, indexing="ij")
+    modes = [((1, 0, 0), 0.7), ((2, -3, 1), -0.4 + 0.2j), ((0, 5, -2), 1.1j), ((6, 0, 0), 0.3)]
+    psi = np.zeros((N, N, N), complex)
+    ref = np.zeros((N, N, N), complex)
+    for (n1, n2, n3), c in modes:
+        p = 2 * np.pi * np.array([n1, n2, n3]) / L
+        if n1 == N // 2:     # Nyquist along x1: use the real cosine, the only sampled mode there
+            f = np.cos(p[0] * X1)
+        else:
+            f = np.exp(1j * (p[0] * X1 + p[1] * X2 + p[2] * X3))
+        psi += c * f
+        ref += c * f * (p @ p) / (2 * m)          # -d^2/dx^2 of a plane wave, over 2m
+    got = O.apply_kinetic(psi, O.K_NR_P2, a, m)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_hk3_squared_is_lattice_p2_plus_m2():
+    N, a, m = 10, 0.25, 1.5
+    psi = rnd((N, N, N), 3)
+    h3 = lambda f: O.apply_kinetic(f, O.K_REL, a, m) + m * f     # sqrt(p^2 + m^2)
+    got = h3(h3(psi))
+    ref = -roll_laplacian_periodic(psi) / (a * a) + m * m * psi
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("N", [5, 6])
+def test_dirichlet_laplacian_is_kronecker_sum(N):
+    psi = rnd((N, N, N), 4)
+    D = sp.csr_matrix(d2_dirichlet(N))
+    I = sp.identity(N)
+    L = sp.kron(sp.kron(D, I), I) + sp.kron(sp.kron(I, D), I) + sp.kron(sp.kron(I, I), D)
+    ref = (L @ psi.ravel()).reshape(N, N, N)
+    np.testing.assert_allclose(O.laplacian_dirichlet(psi), ref, atol=1e-13)
+
+
+def test_fdtd_sine_modes_have_closed_form_eigenvalues():
+    N, a, m = 9, 0.5, 1.3
+    i = np.arange(N)
+    for n in [(1, 1, 1), (2, 1, 3), (9, 4, 1)]:
+        f = [np.sin(np.pi * nl * (i + 1) / (N + 1)) for nl in n]
+        psi = f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]
+        lam = (2 / (m * a * a)) * sum(math.sin(math.pi * nl / (2 * (N + 1))) ** 2 for nl in n)
+        got = O.apply_kinetic(psi, O.K_FDTD, a, m)
+        np.testing.assert_allclose(got, lam * psi, atol=1e-12)
+
+
+# ------------------------------------------------------------ step operators
+
+def dense_kinetic(kind, N, a, m):
+    if kind == O.K_NR_P2:
+        D = symbol_matrix_1d(N, lambda k: k * k / (2 * m * a * a))
+        assert np.abs(D.imag).max() < 1e-12 * np.abs(D).max()    # +-k pairs and k = pi: real
+        return kron_sum(D.real)
+    P2 = -kron_sum(d2_periodic(N)) / (a * a)          # lattice p^2, stencil-built
+    if kind == O.K_NR_SIN2:
+        return P2 / (2 * m)
+    w, U = np.linalg.eigh(P2)
+    return (U * (np.sqrt(np.maximum(w, 0) + m * m) - m)) @ U.T
+
+
+@pytest.mark.parametrize("kind", [O.K_NR_P2, O.K_NR_SIN2, O.K_REL])
+def test_split_step_equals_dense_exponential(kind):
+    N, a, m, dt = 6, 0.3, 1.2, 0.01
+    V = rnd((N, N, N), 5) * 3.0
+    psi = rnd((N, N, N), 6)
+    K = dense_kinetic(kind, N, a, m)
+    h = np.exp(-0.5 * dt * V.ravel())
+    Smat = (h[:, None] * sla.expm(-dt * K)) * h[None, :]
+    ref = (Smat @ psi.ravel()).reshape(N, N, N)
+    T = O.kinetic_symbol(kind, N, a, m)
+    got = O.step_split(psi, T, V, dt)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_fdtd_step_at_constant_potential_scales_sine_modes():
+    # constant V: the step maps an eigenmode of L_D to ((1 - dt V/2) - dt lam)/(1 + dt V/2) times itself
+    N, a, m, dt, v0 = 7, 0.5, 1.0, 0.02, 2.5 + 0.5j
+    i = np.arange(N)
+    f = [np.sin(np.pi * nl * (i + 1) / (N + 1)) for nl in (1, 2, 3)]
+    psi = f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]
+    # eigenvalue of H_K^(0) from the 1D Dirichlet matrix (no closed form reused)
+    lam = sum(np.linalg.eigvalsh(-d2_dirichlet(N) / (2 * m * a * a))[nl - 1] for nl in (1, 2, 3))
+    V = np.full((N, N, N), v0)
+    got = O.step_fdtd(psi, V, dt, a, m)
+    # backward-Euler-in-V / forward-Euler-in-K map of d psi/dtau = -(K + V) psi
+    mu = (1 - dt * v0 / 2 - dt * lam) / (1 + dt * v0 / 2)
+    np.testing.assert_allclose(got, mu * psi, atol=1e-13)
+
+
+# -------------------------------------------- separable harmonic oscillator
+
+def ho_1d(kind, N, a, m, dt):
+    x = O.coords(N, a)
+    V1 = np.diag(0.5 * x * x)
+    if kind == O.K_NR_P2:
+        K1 = symbol_matrix_1d(N, lambda k: k * k / (2 * m * a * a)).real
+    elif kind == O.K_NR_SIN2:
+        K1 = -d2_periodic(N) / (2 * m * a * a)
+    else:
+        K1 = -d2_dirichlet(N) / (2 * m * a * a)
+    return K1, V1
+
+
+@pytest.mark.parametrize("kind", [O.K_NR_P2, O.K_NR_SIN2])
+def test_ho_fft_converges_to_tensor_products_of_1d_step_eigenvectors(kind):
+    N, a, m = 16, 0.5, 1.0
+    dt = a * a / 8
+    K1, V1 = ho_1d(kind, N, a, m, dt)
+    h1 = np.exp(-0.5 * dt * np.diag(V1))
+    S1 = (h1[:, None] * sla.expm(-dt * K1)) * h1[None, :]
+    mu, U = np.linalg.eigh(S1)
+    v0, v1 = U[:, -1], U[:, -2]                       # dominant 1D modes
+    H1 = K1 + V1
+    e00 = v0 @ H1 @ v0
+    e11 = v1 @ H1 @ v1
+    p = S.Problem(N=N, a=a, m=m, kinetic=kind, vkind=S.V_HARMONIC, vparams=(1.0,), k=3,
+                  dt=dt, steps=1600, seed=7)
+    res = O.solve(p)
+    E = res["energies"]
+    np.testing.assert_allclose(E.real, [3 * e00, 2 * e00 + e11, 2 * e00 + e11], rtol=0, atol=1e-10)
+    assert np.abs(E.imag).max() < 1e-14
+    # energies of the lattice H itself: within the O(dt^4) Strang bias
+    ev = np.linalg.eigvalsh(H1)
+    np.testing.assert_allclose(E.real, [3 * ev[0], 2 * ev[0] + ev[1], 2 * ev[0] + ev[1]],
+                               rtol=0, atol=5e-7)
+    psi0 = res["states"][0].ravel()
+    t0 = np.kron(np.kron(v0, v0), v0)
+    assert abs(abs(np.vdot(t0, psi0)) - 1) < 1e-10
+    # the two excited states lie in span{v1 v0 v0, v0 v1 v0, v0 v0 v1}
+    B = np.stack([np.kron(np.kron(v1, v0), v0), np.kron(np.kron(v0, v1), v0),
+                  np.kron(np.kron(v0, v0), v1)], axis=1)
+    for s in res["states"][1:]:
+        r = s.ravel() - B @ (B.T @ s.ravel())
+        assert np.linalg.norm(r) < 1e-8
+
+
+def test_fdtd_ho_fixed_point_is_self_consistent_separable_problem():
+    # fixed point psi' = mu psi of the A/B step solves (H_K + c V) psi = eps psi with
+    # c = (1 + mu)/2 and mu = 1 - dt eps; H_K + c V is separable, so psi0 = w x w x w
+    N, a, m = 14, 0.5, 1.0
+    dt = a * a / 8
+    K1, V1 = ho_1d(O.K_FDTD, N, a, m, dt)
+    c = 1.0
+    for _ in range(200):
+        w_e, w_U = np.linalg.eigh(K1 + c * V1)
+        eps = 3 * w_e[0]
+        c_new = 1 - dt * eps / 2
+        if abs(c_new - c) < 1e-16:
+            break
+        c = c_new
+    w = w_U[:, 0]
+    e_ref = 3 * (w @ (K1 + V1) @ w)
+    p = S.Problem(N=N, a=a, m=m, kinetic=O.K_FDTD, vkind=S.V_HARMONIC, vparams=(1.0,), k=1,
+                  dt=dt, steps=2000, seed=8)
+    res = O.solve(p)
+    assert abs(res["energies"][0].real - e_ref) < 1e-11
+    t0 = np.kron(np.kron(w, w), w)
+    assert abs(abs(np.vdot(t0, res["states"][0].ravel())) - 1) < 1e-10
+
+
+def test_continuum_ho_levels_config1():
+    # omega (n + 3/2) with omega = 1; H_K^(1) at a = 0.25 is spectrally accurate
+    p = S.config1()
+    res = O.solve(p)
+    E = np.sort(res["energies"].real)
+    np.testing.assert_allclose(E, [1.5, 2.5, 2.5], atol=2e-5)
+    # and the lattice-exact values of the separable 32-site problem
+    K1, V1 = ho_1d(O.K_NR_P2, p.N, p.a, p.m, p.dt)
+    ev = np.linalg.eigvalsh(K1 + V1)
+    np.testing.assert_allclose(E, [3 * ev[0], 2 * ev[0] + ev[1], 2 * ev[0] + ev[1]], atol=1e-8)
+
+
+# ------------------------------------------------ dense non-separable checks
+
+def cornell(N, a, alpha, sigma):
+    x = O.coords(N, a)
+    r = np.sqrt(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+    rf = np.maximum(r, a / 2)
+    return -alpha / rf + sigma * rf
+
+
+@pytest.mark.parametrize("kind", [O.K_REL, O.K_NR_P2])
+def test_dense_8cube_cornell_top_states(kind):
+    N, a, m, dt = 8, 0.25, 1.5, 0.05
+    V = cornell(N, a, 0.4, 0.2)
+    K = dense_kinetic(kind, N, a, m)
+    h = np.exp(-0.5 * dt * V.ravel())
+    Smat = (h[:, None] * sla.expm(-dt * K)) * h[None, :]
+    mu, U = np.linalg.eigh((Smat + Smat.T) / 2)
+    mu, U = mu[::-1], U[:, ::-1]
+    # levels 2..4 form a degenerate 1P triplet (cubic symmetry)
+    assert abs(mu[2] - mu[4]) < 1e-12 * mu[2] and mu[1] - mu[2] > 1e-4
+    H = K + np.diag(V.ravel())
+    p = S.Problem(N=N, a=a, m=m, kinetic=kind, vkind=S.V_CORNELL, vparams=(0.4, 0.2, a / 2),
+                  k=3, dt=dt, steps=8000, seed=9)     # tau = 400: next level 0.09 above
+    res = O.solve(p)
+    st = res["states"].reshape(3, -1).T
+    # nested subspaces: span of the first j oracle states = span of the top-j S eigenvectors
+    for j in (1, 2):
+        Pa = st[:, :j] @ st[:, :j].conj().T
+        Pb = U[:, :j] @ U[:, :j].T
+        assert np.linalg.norm(Pa - Pb, 2) < 1e-8
+    # the third state lies in the degenerate triplet's eigenspace
+    trip = U[:, 2:5]
+    assert np.linalg.norm(st[:, 2] - trip @ (trip.T @ st[:, 2])) < 1e-8
+    ritz = np.array([U[:, i] @ H @ U[:, i] for i in range(3)])
+    np.testing.assert_allclose(np.sort(res["energies"].real), np.sort(ritz), atol=1e-10)
+    np.testing.assert_allclose(np.sort(res["energies"].real), np.linalg.eigvalsh(H)[:3], atol=5e-4)
+
+
+def test_dense_8cube_complex_potential_invariant_subspaces():
+    # non-Hermitian S: the iteration converges to S's Schur vectors, i.e. nested
+    # invariant subspaces ordered by |eigenvalue|
+    N, a, m, dt = 8, 0.25, 1.5, 0.05
+    V = cornell(N, a, 0.4, 0.2) + 1j * S.orbit_uniform_field(N, 11, 0.0, 0.5)
+    K = dense_kinetic(O.K_REL, N, a, m)
+    h = np.exp(-0.5 * dt * V.ravel())
+    Smat = (h[:, None] * sla.expm(-dt * K)) * h[None, :]
+    w, vr = np.linalg.eig(Smat)
+    idx = np.argsort(-np.abs(w))
+    # levels 0, 1 are isolated; 2..4 is the 1P triplet, split by the perturbation
+    # by less than the run can resolve, and level 5 sits 0.09 above it
+    assert np.abs(w[idx[1]]) - np.abs(w[idx[2]]) > 1e-3
+    p = S.Problem(N=N, a=a, m=m, kinetic=O.K_REL, vkind=S.V_GRID, k=3, dt=dt, steps=8000, seed=10)
+    states = O.prepare(p.init_states(), [0, 0, 0], True)
+    states = O.evolve(states, O.K_REL, a, m, V, dt, 8000, 50, [0, 0, 0])
+    st = np.stack([s.ravel() for s in states], axis=1)
+    for j in (1, 2):
+        Q, _ = np.linalg.qr(vr[:, idx[:j]])
+        Pa = st[:, :j] @ st[:, :j].conj().T
+        assert np.linalg.norm(Pa - Q @ Q.conj().T, 2) < 1e-8
+    Q5, _ = np.linalg.qr(vr[:, idx[:5]])
+    assert np.linalg.norm(st[:, 2] - Q5 @ (Q5.conj().T @ st[:, 2])) < 1e-8
+    # complex ground-state energy = Rayleigh quotient of S's dominant eigenvector with H
+    H = K + np.diag(V.ravel())
+    E = O.energies(states, O.K_REL, a, m, V)
+    v0 = vr[:, idx[0]] / np.linalg.norm(vr[:, idx[0]])
+    assert abs(E[0] - np.vdot(v0, H @ v0)) < 1e-10
+    assert E[0].imag > 0     # Im V >= 0 moves the level up in Im E
+
+
+def test_free_particle_closed_forms():
+    N, a, m = 12, 0.5, 1.0
+    # periodic, V = 0: uniform ground state with E = 0
+    p = S.Problem(N=N, a=a, m=m, kinetic=O.K_NR_SIN2, vkind=S.V_GRID, k=1, dt=0.05, steps=1500, seed=12)
+    states = O.prepare(p.init_states(), [0], True)
+    Z = np.zeros((N, N, N), complex)
+    states = O.evolve(states, p.kinetic, a, m, Z, p.dt, p.steps, 50, [0])
+    E = O.energies(states, p.kinetic, a, m, Z)
+    assert abs(E[0]) < 1e-12
+    assert np.allclose(np.abs(states[0]), 1 / N ** 1.5, atol=1e-9)
+    # Dirichlet, V = 0: 3 (2/(M a^2)) sin^2(pi / (2 (N+1)))
+    states = O.prepare(p.init_states(), [0], False)
+    states = O.evolve(states, O.K_FDTD, a, m, Z, 0.05, 4000, 50, [0])
+    E = O.energies(states, O.K_FDTD, a, m, Z)
+    ref = 3 * (2 / (m * a * a)) * math.sin(math.pi / (2 * (N + 1))) ** 2
+    assert abs(E[0].real - ref) < 1e-10
+
+
+def test_decay_rate_matches_energy_to_dt_squared():
+    # general solution Psi(tau) ~ a0 Psi_0 exp(-E_0 tau): norm decay of the converged state
+    N, a, m = 16, 0.5, 1.0
+    errs = []
+    for dt in (0.04, 0.02):
+        p = S.Problem(N=N, a=a, m=m, kinetic=O.K_NR_SIN2, vkind=S.V_HARMONIC, vparams=(1.0,),
+                      k=1, dt=dt, steps=int(30 / dt), seed=13)
+        res = O.solve(p)
+        V = O.problem_potential(p)
+        T = O.kinetic_symbol(p.kinetic, N, a, m)
+        psi = res["states"][0]
+        nxt = O.step_split(psi, T, V, dt)
+        rate = -math.log(np.linalg.norm(nxt)) / dt
+        errs.append(abs(rate - res["energies"][0].real))
+    assert errs[0] < 0.05 * 0.04 ** 2 * 10
+    assert 3.0 < errs[0] / errs[1] < 5.0          # O(dt^2)
+
+
+# ------------------------------------------------------------------ parity
+
+def test_parity_projectors_algebra_and_paper_identities():
+    N, a = 12, 0.5
+    psi = rnd((N, N, N), 14)
+    for sec in (O.S_PLUS, O.S_MINUS, O.S_PK1, O.S_PK2, O.S_PK3):
+        P1 = O.parity_project(psi, sec)
+        np.testing.assert_allclose(O.parity_project(P1, sec), P1, atol=1e-14)
+    np.testing.assert_allclose(O.parity_project(psi, O.S_PLUS) + O.parity_project(psi, O.S_MINUS),
+                               psi, atol=1e-14)
+    for k in (O.S_PK1, O.S_PK2, O.S_PK3):
+        assert np.abs(O.parity_project(O.parity_project(psi, k), O.S_PLUS)).max() < 1e-14
+    # reflection is x -> -x about the origin site N/2
+    x = O.coords(N, a)
+    f = np.exp(x)[:, None, None] * np.ones((1, N, N))
+    g = O.reflect(f, (0,))
+    np.testing.assert_allclose(g[1:], np.exp(-x)[1:, None, None] * np.ones((1, N, N)), rtol=1e-14)
+    # commute with H for the symmetric harmonic potential
+    V = O.potential(N, a, O.V_HARMONIC, (1.0,))
+    for sec in (O.S_PLUS, O.S_PK3):
+        lhs = O.apply_hamiltonian(O.parity_project(psi, sec), O.K_REL, a, 1.5, V)
+        rhs = O.parity_project(O.apply_hamiltonian(psi, O.K_REL, a, 1.5, V), sec)
+        np.testing.assert_allclose(lhs, rhs, atol=1e-11)
+    # P^+ psi_s = psi_s, P^-_{p_k} psi_s = 0, P^+ psi_p = 0, P^-_{p_3} psi_pz = psi_pz
+    K1, V1 = ho_1d(O.K_NR_SIN2, N, a, 1.0, 0.01)
+    _, U = np.linalg.eigh(K1 + V1)
+    v0, v1 = U[:, 0], U[:, 1]
+    s = np.einsum("i,j,k->ijk", v0, v0, v0)
+    pz = np.einsum("i,j,k->ijk", v0, v0, v1)
+    np.testing.assert_allclose(O.parity_project(s, O.S_PLUS), s, atol=1e-14)
+    assert np.abs(O.parity_project(s, O.S_PK3)).max() < 1e-14
+    assert np.abs(O.parity_project(pz, O.S_PLUS)).max() < 1e-14
+    np.testing.assert_allclose(O.parity_project(pz, O.S_PK3), pz, atol=1e-14)
+
+
+def test_dirichlet_reflection_maps_edge_to_wall():
+    N = 6
+    psi = rnd((N, N, N), 15)
+    r = O.reflect(psi, (2,), periodic=False)
+    assert np.all(r[:, :, 0] == 0)
+    np.testing.assert_array_equal(r[:, :, 1:], psi[:, :, ::-1][:, :, :-1])
+
+
+# -------------------------------------------------------------- Gram-Schmidt
+
+def test_gram_schmidt_orthonormal_and_chunk_independent():
+    N, a, m = 10, 0.5, 1.0
+    p = S.Problem(N=N, a=a, m=m, kinetic=O.K_NR_SIN2, vkind=S.V_HARMONIC, vparams=(1.0,), k=3,
+                  dt=0.02, steps=60, seed=16)
+    V = O.problem_potential(p)
+    outs = []
+    for K in (1, 10, 60):
+        st = O.prepare(p.init_states(), [0, 0, 0], True)
+        st = O.evolve(st, p.kinetic, a, m, V, p.dt, p.steps, K, [0, 0, 0])
+        G = np.array([[O.inner(x, y) for y in st] for x in st])
+        np.testing.assert_allclose(G, np.eye(3), atol=1e-13)
+        outs.append(np.stack(st))
+    for o in outs[1:]:
+        for i in range(3):
+            assert abs(abs(np.vdot(o[i].ravel(), outs[0][i].ravel())) - 1) < 1e-10
+    # sectors are not mixed: a P^+ state and a P^-_{p3} state stay in their sectors
+    st = O.prepare(p.init_states(), [O.S_PLUS, O.S_PLUS, O.S_PK3], True)
+    assert abs(O.inner(st[0], st[2])) < 1e-14
+    np.testing.assert_allclose(O.parity_project(st[2], O.S_PK3), st[2], atol=1e-14)
+
+
+# ------------------------------------------------------------- potentials
+
+def natural_spline_eval(xk, yk, xq):
+    """Natural cubic spline written out: tridiagonal solve for the second derivatives."""
+    n = len(xk)
+    h = np.diff(xk)
+    A = np.zeros((n, n))
+    rhs = np.zeros(n)
+    A[0, 0] = A[-1, -1] = 1.0
+    for i in range(1, n - 1):
+        A[i, i - 1] = h[i - 1]
+        A[i, i] = 2 * (h[i - 1] + h[i])
+        A[i, i + 1] = h[i]
+        rhs[i] = 6 * ((yk[i + 1] - yk[i]) / h[i] - (yk[i] - yk[i - 1]) / h[i - 1])
+    M = np.linalg.solve(A, rhs)
+    j = np.clip(np.searchsorted(xk, xq, side="right") - 1, 0, n - 2)
+    t0 = xk[j + 1] - xq
+    t1 = xq - xk[j]
+    hj = h[j]
+    return (M[j] * t0 ** 3 + M[j + 1] * t1 ** 3) / (6 * hj) + (yk[j] / hj - M[j] * hj / 6) * t0 \
+        + (yk[j + 1] / hj - M[j + 1] * hj / 6) * t1
+
+
+def test_potentials():
+    N, a = 16, 0.5
+    x = O.coords(N, a)
+    c = N // 2
+    Vc = O.potential(N, a, O.V_CORNELL, (0.4, 0.2, a / 2))
+    assert abs(Vc[c, c, c] - (-0.4 / (a / 2) + 0.2 * a / 2)) < 1e-15
+    r = math.sqrt(x[3] ** 2 + x[c] ** 2 + x[11] ** 2)
+    assert abs(Vc[3, c, 11] - (-0.4 / r + 0.2 * r)) < 1e-14
+    Vh = O.potential(N, a, O.V_HARMONIC, (1.0,))
+    assert abs(Vh[0, 0, 0] - 0.5 * 3 * x[0] ** 2) < 1e-13
+    knots = S.spline_knots(N * a, 77)
+    Vs = O.potential(N, a, O.V_RADIAL_SPLINE, knots=knots)
+    rr = O.radius(N, a)
+    np.testing.assert_allclose(Vs.real, natural_spline_eval(knots[:, 0], knots[:, 1], rr), atol=1e-12)
+    assert rr.max() <= knots[-1, 0] + 1e-12
+
+
+def test_orbit_field_is_reflection_symmetric():
+    N = 10
+    f = S.orbit_uniform_field(N, 5, 0.0, 0.01)
+    np.testing.assert_array_equal(f, O.reflect(f, (0, 1)))
+    np.testing.assert_array_equal(f, O.reflect(f, (2,)))
+    assert 0 <= f.min() and f.max() < 0.01
+    assert len(np.unique(f)) > N ** 3 // 8     # one draw per orbit, not a constant
+
+
+def test_relativistic_term_tends_to_nonrelativistic_limit():
+    N, a = 12, 0.5
+    x = O.coords(N, a)
+    g = np.exp(-(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2) / 2)
+    rel = []
+    for m in (10.0, 20.0, 40.0):
+        h3 = O.apply_kinetic(g, O.K_REL, a, m)
+        h2 = O.apply_kinetic(g, O.K_NR_SIN2, a, m)
+        rel.append(np.linalg.norm(h3 - h2) / np.linalg.norm(h2))
+    assert rel[0] > rel[1] > rel[2]
+    assert 3.0 < rel[0] / rel[1] < 5.0     # O(p^2 / M^2)
