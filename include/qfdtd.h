@@ -1,0 +1,197 @@
+/*
+ * qfdtd.h -- C ABI of the MI355X (gfx950) imaginary-time Schroedinger solver.
+ *
+ * The library evolves k wavefunctions on a periodic or walled N^3 lattice in
+ * imaginary time and extracts the lowest states and their energies, as
+ * described in arXiv:2211.10185 (QuantumFDTD v3):
+ *
+ *   H = H_K + V                                        Sec. 2, eq. (eq_schro)
+ *   H_K^(0) 7-point finite differences, Dirichlet      Sec. 2, eq. (HK0); Sec. 1
+ *   H_K^(1) FFT, sum k_l^2 / (2 A^2 M)                 Sec. 2, eq. (HK1)
+ *   H_K^(2) FFT, 4 sum sin^2(k_l/2) / (2 A^2 M)        Sec. 2, eq. (HK2)
+ *   H_K^(3) FFT, sqrt(4 sum sin^2(k_l/2) + (AM)^2)/A   Sec. 2, eq. (HK3)
+ *   k_l = A p_l in {-pi + 2pi/N, ..., pi}              Sec. 2, after (HK3)
+ *   -d/dtau Psi = H Psi; Psi = sum a_n Psi_n e^{-E_n tau}   Sec. 2, eq. (eq_iterat)
+ *   excited states by orthogonal projection            Sec. 1
+ *   parity projectors P^+, P^-, P^-_{p_k}              Sec. 3, beside Fig. 1
+ *
+ * Readings taken where the paper defers to its references:
+ *   - FFT kinds use the symmetric split step  h F^-1[e^{-dt T} F[h psi]],
+ *     h = e^{-dt V/2};  H_K^(0) uses psi <- A psi - B dt H_K^(0) psi with
+ *     A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2).
+ *   - H_K^(0) is the standard 7-point Laplacian over A^2, times -1/(2M).
+ *   - H_K^(3) is evolved and reported with the rest mass removed (T - M).
+ *   - Site i_l has coordinate x_l = (i_l - N/2) A (origin on site N/2).
+ *   - The k states are orthonormalised (Gram-Schmidt in state order, within
+ *     each parity sector) every `measure_every` steps and after the last one.
+ *   - Energies are the Rayleigh quotients <psi_i|H|psi_i>, complex when V is.
+ *
+ * Conventions
+ *   - Every call returns a qfdtd_status; nothing throws across the ABI.
+ *   - Host arrays are complex128, interleaved (re, im), C order with x3
+ *     fastest: element (i1, i2, i3) at 2*((i1*N + i2)*N + i3).
+ *   - The context owns all device memory it allocates (through the optional
+ *     allocator hook, else hipMalloc).  Input arrays are copied during the
+ *     call and stay owned by the caller; output arrays are caller-owned.
+ *   - All device work is ordered on the context's stream.  Calls that return
+ *     host data synchronise that stream before returning.
+ *   - One context must not be used from two host threads at once.
+ *   - After QFDTD_E_NUMERIC (NaN/Inf or a collapsed norm) or QFDTD_E_DEVICE
+ *     the context is poisoned: qfdtd_evolve returns QFDTD_E_STATE until every
+ *     state has been replaced with qfdtd_set_state.
+ */
+#ifndef QFDTD_H
+#define QFDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QFDTD_OK = 0,
+  QFDTD_E_INVALID = -1,        /* bad argument (null pointer, a <= 0, k out of range, ...) */
+  QFDTD_E_UNSUPPORTED_N = -2,  /* N odd, N < 8, N > 512, or (FFT kinds) N not 2^a 3^b 5^c */
+  QFDTD_E_UNSTABLE_DT = -3,    /* dt <= 0, or H_K^(0) with dt > M A^2 / 3 */
+  QFDTD_E_NOMEM = -4,          /* device allocation failed */
+  QFDTD_E_DEVICE = -5,         /* a HIP runtime call failed */
+  QFDTD_E_NUMERIC = -6,        /* NaN/Inf or non-positive norm met during orthonormalisation */
+  QFDTD_E_STATE = -7           /* context poisoned, or states not set */
+} qfdtd_status;
+
+/* H_K^(0..3), Sec. 2 eqs. (HK0)-(HK3). */
+typedef enum {
+  QFDTD_K_FDTD = 0,
+  QFDTD_K_NR_P2 = 1,
+  QFDTD_K_NR_SIN2 = 2,
+  QFDTD_K_REL = 3
+} qfdtd_kinetic;
+
+typedef enum {
+  QFDTD_V_GRID = 0,           /* V is `grid` */
+  QFDTD_V_HARMONIC = 1,       /* V = p[0] r^2 / 2 */
+  QFDTD_V_CORNELL = 2,        /* V = -p[0]/r_f + p[1] r_f,  r_f = max(r, p[2]) */
+  QFDTD_V_COULOMB = 3,        /* V = -p[0]/r_f,             r_f = max(r, p[1]) */
+  QFDTD_V_RADIAL_SPLINE = 4   /* natural cubic spline through (knots[2j], knots[2j+1]) = (r_j, V_j) */
+} qfdtd_vkind;
+
+/* Parity sectors (Sec. 3).  Reflection R_l maps site i_l to N - i_l
+ * (mod N on the periodic lattice; onto the wall, where psi = 0, for FDTD).
+ *   P^+ = (1 + R)/2, P^- = (1 - R)/2 with R = R_1 R_2 R_3,
+ *   P^-_{p_k} = (1 + R_i R_j)(1 - R_k)/4, {i, j, k} = {1, 2, 3}. */
+typedef enum {
+  QFDTD_S_NONE = 0,
+  QFDTD_S_PLUS = 1,
+  QFDTD_S_MINUS = 2,
+  QFDTD_S_PK1 = 3,
+  QFDTD_S_PK2 = 4,
+  QFDTD_S_PK3 = 5
+} qfdtd_sector;
+
+typedef struct {
+  int32_t kind;              /* qfdtd_vkind */
+  double p[4];               /* parameters, see qfdtd_vkind */
+  const double *knots;       /* QFDTD_V_RADIAL_SPLINE: n_knots (r, V) pairs, r strictly increasing; host, copied */
+  int32_t n_knots;           /* >= 3 */
+  const double *grid;        /* host complex128 N^3 (re, im): the potential for QFDTD_V_GRID, otherwise
+                                an addition to the analytic V (e.g. an imaginary part); NULL = none; copied */
+} qfdtd_potential;
+
+typedef void *(*qfdtd_alloc_fn)(size_t bytes, void *user);
+typedef void (*qfdtd_free_fn)(void *ptr, void *user);
+
+typedef struct {
+  int32_t precision;          /* 0: complex64 states, FP32 transforms, FP64 reductions; 1: complex128 throughout */
+  int32_t n_states;           /* k, 1..8 */
+  const int32_t *sectors;     /* k qfdtd_sector values, or NULL for all QFDTD_S_NONE; copied */
+  int32_t measure_every;      /* K >= 1: orthonormalise every K steps (0 = default 50) */
+  int32_t trace_energies;     /* nonzero: also record E_i after every K-step chunk (qfdtd_energy_trace) */
+  void *hip_stream;           /* hipStream_t for all work; NULL = the null stream */
+  qfdtd_alloc_fn dev_alloc;   /* optional device allocator (e.g. a framework caching allocator) */
+  qfdtd_free_fn dev_free;     /* must be given together with dev_alloc */
+  void *alloc_user;           /* passed to dev_alloc / dev_free */
+} qfdtd_options;
+
+typedef struct qfdtd_ctx qfdtd_ctx;
+
+/* Create a solver for an N^3 lattice of spacing a and mass m with kinetic term
+ * `kinetic` and potential `V` (Sec. 2).  V is evaluated on the device in FP64 at
+ * x_l = (i_l - N/2) a.  The states are unset until qfdtd_set_state.  On failure
+ * *out is NULL and nothing is leaked.  opt may be NULL (complex64, k = 3, K = 50). */
+qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_t kinetic,
+                          const qfdtd_potential *V, const qfdtd_options *opt);
+
+/* Replace state i (0 <= i < k) with the host complex128 array psi (N^3 (re, im)).
+ * The states are projected onto their sectors and orthonormalised before the next
+ * evolution step (so the array need not be normalised).  Clears a poisoned context
+ * once every state has been set again. */
+qfdtd_status qfdtd_set_state(qfdtd_ctx *c, int32_t i, const double *psi);
+
+/* Same, from a device buffer in the context's state precision (complex64 or
+ * complex128, interleaved, N^3 elements).  Stream-ordered; no synchronisation. */
+qfdtd_status qfdtd_set_state_device(qfdtd_ctx *c, int32_t i, const void *psi_dev);
+
+/* Advance all k states by `steps` imaginary-time steps of size dt (Sec. 2, eq.
+ * (eq_iterat)), orthonormalising every K steps and after the last one.  Enqueued on
+ * the stream; returns without waiting, except that a NaN/Inf found by an earlier
+ * call is reported here.  QFDTD_E_UNSTABLE_DT for H_K^(0) when dt > m a^2 / 3. */
+qfdtd_status qfdtd_evolve(qfdtd_ctx *c, int64_t steps, double dt);
+
+/* Energies of states 0..k-1 (energies[2i], energies[2i+1] = Re, Im of E_i; H_K^(3)
+ * energies exclude the rest mass) and, if psi is not NULL, the states as host
+ * complex128 [k][N^3] normalised to sum |psi|^2 = 1.  Synchronises the stream. */
+qfdtd_status qfdtd_states(qfdtd_ctx *c, int32_t k, double *energies, double *psi);
+
+/* Energies to host as above (synchronising), states copied device-to-device into
+ * psi_dev ([k][N^3] in the state precision) on the stream. */
+qfdtd_status qfdtd_states_device(qfdtd_ctx *c, int32_t k, double *energies, void *psi_dev);
+
+/* Energies recorded after each chunk when trace_energies was set: out[(t*k + i)*2 + {0,1}]
+ * for t < min(cap, recorded); *n = number of recorded chunks.  Synchronises. */
+qfdtd_status qfdtd_energy_trace(qfdtd_ctx *c, double *out, int64_t cap, int64_t *n);
+
+/* Evolve several contexts together: member j advances steps[j] steps of dt[j].  Each
+ * pass of the step is one launch over the tiles of every member that takes it, so
+ * lattices of different N, kinetic term and potential share the GPU.  All members
+ * must have the same precision and the same stream.  Results are identical to
+ * calling qfdtd_evolve on each member alone. */
+qfdtd_status qfdtd_batch_evolve(qfdtd_ctx *const *members, int32_t n, const int64_t *steps,
+                                const double *dt);
+
+/* Batched energy readout: energies[2*(j*kmax + i) + {0,1}] for member j, state i < k_j.
+ * kmax = largest k among the members.  Synchronises the (common) stream. */
+qfdtd_status qfdtd_batch_energies(qfdtd_ctx *const *members, int32_t n, double *energies);
+
+/* Device bytes the context for this problem would hold (for admission control). */
+size_t qfdtd_footprint(int32_t N, int32_t kinetic, int32_t precision, int32_t n_states);
+
+/* Launch-level timing of the evolution kernels: when enabled, the context records a
+ * pair of HIP events on its stream around every sampled launch, per kernel class.
+ * qfdtd_kernel_stats returns, for class `cls` (0 plane, 1 row, 2 column, 3 stencil,
+ * 4 measurement), the number of timed launches, their mean duration in ms and the
+ * algorithmic bytes one launch of that class moves (read once + written once).
+ * Synchronises the stream. */
+qfdtd_status qfdtd_enable_kernel_timing(qfdtd_ctx *c, int32_t every);
+qfdtd_status qfdtd_kernel_stats(qfdtd_ctx *c, int32_t cls, int64_t *count, double *mean_ms,
+                                double *bytes_per_launch);
+
+/* Forward (sign = -1) or inverse (sign = +1, including 1/N^3) 3D DFT of state i in
+ * place, in the state precision, with the library's transform kernels.  For checks
+ * of the transform against a reference; FFT kinds only. */
+qfdtd_status qfdtd_transform_state(qfdtd_ctx *c, int32_t i, int32_t sign);
+
+/* Device pointer of state i (state precision, N^3 interleaved complex). */
+qfdtd_status qfdtd_state_pointer(qfdtd_ctx *c, int32_t i, void **ptr);
+
+void qfdtd_destroy(qfdtd_ctx *c);
+
+/* Message for the last failing call on c (or of the last failed create when c is NULL). */
+const char *qfdtd_last_error(const qfdtd_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QFDTD_H */

@@ -1,0 +1,627 @@
+// Setup, stencil, projection and FP64 measurement kernels.
+//
+//  k_twiddles     FP64 generation of roots of unity and kinetic symbols  (Sec. 2, text after HK3)
+//  k_potential    FP64 V(r) on the lattice (harmonic, Cornell, Coulomb, radial spline, grid)
+//  k_dt_tables    e^{-dt V/2}, e^{-dt V}, e^{-dt t(k_j)} for the current dt (FP64, stored
+//                 in the state precision)
+//  k_stencil      H_K^(0) step psi' = A psi + B dt/(2 M a^2) L psi            (Sec. 2, eq. HK0)
+//  k_parity       P^+, P^-, P^-_{p_k} by mirrored gathers                    (Sec. 3, Fig. 1 text)
+//  k_gram ...     FP64 Gram matrix, Cholesky, Psi <- Psi R^{-1}              (Sec. 1: orthogonal projection)
+//  k_energy_*     FP64 <psi|V|psi>, <psi|H_K|psi>, <psi|psi>                (Sec. 2, general solution)
+//
+// All reductions are two-level with a fixed grid and a fixed summation order,
+// so repeated runs, and a member run alone or inside a batch, give identical bits.
+#include "common.h"
+
+namespace qf {
+
+constexpr int EW_PER_THREAD = 4;   // sites per thread of the elementwise kernels
+
+__host__ __device__ inline int ew_tiles(long long n) {
+  long long per = (long long)RED_THREADS * EW_PER_THREAD;
+  return (int)((n + per - 1) / per);
+}
+
+// ------------------------------------------------------------------ tables
+
+// roots of unity w^m = e^{-2 pi i m/N}, FP64 and state precision; kinetic per-axis symbols
+template <typename T>
+__global__ void k_twiddles(C<T> *tw, double2 *tw64, double *ksym64, int N, int kin, double a, double m) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  double s, c;
+  sincospi(2.0 * (double)j / (double)N, &s, &c);
+  tw64[j] = make_double2(c, -s);
+  tw[j] = mkc<T>((T)c, (T)-s);
+  // lattice momentum k = 2 pi j'/N with j' in (-N/2, N/2]
+  const int jp = (j <= N / 2) ? j : j - N;
+  const double k = 2.0 * M_PI * (double)jp / (double)N;
+  const double sh = sinpi((double)jp / (double)N);   // sin(k/2)
+  double v = 0.0;
+  if (kin == KIN_P2) v = k * k / (2.0 * m * a * a);
+  else if (kin == KIN_SIN2) v = 4.0 * sh * sh / (2.0 * m * a * a);
+  else if (kin == KIN_REL) v = 4.0 * sh * sh / (a * a);
+  ksym64[j] = v;
+}
+
+// Potential kinds (match the public header)
+enum { PV_GRID = 0, PV_HARMONIC = 1, PV_CORNELL = 2, PV_COULOMB = 3, PV_SPLINE = 4 };
+
+// knots: [nk] r, [nk] V, [nk] second derivatives of the natural spline
+__device__ double spline_eval(const double *kn, int nk, double r) {
+  const double *xr = kn, *yv = kn + nk, *M = kn + 2 * nk;
+  int lo = 0, hi = nk - 2;
+  while (lo < hi) {       // largest j <= nk-2 with x_j <= r (j = 0 below the first knot)
+    int mid = (lo + hi + 1) >> 1;
+    if (xr[mid] <= r) lo = mid; else hi = mid - 1;
+  }
+  const int j = lo;
+  const double h = xr[j + 1] - xr[j];
+  const double t0 = xr[j + 1] - r, t1 = r - xr[j];
+  return (M[j] * t0 * t0 * t0 + M[j + 1] * t1 * t1 * t1) / (6.0 * h) + (yv[j] / h - M[j] * h / 6.0) * t0 +
+         (yv[j + 1] / h - M[j + 1] * h / 6.0) * t1;
+}
+
+// v64: real [N^3] (vcomplex = 0) or complex [N^3] (vcomplex = 1); add: complex grid or null
+__global__ void k_potential(double *v64, int vcomplex, int N, double a, int kind, double p0, double p1,
+                            double p2, const double *knots, int nk, const double2 *add) {
+  const size_t N3 = (size_t)N * N * N;
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N3) return;
+  const int i3 = (int)(g % N), i2 = (int)((g / N) % N), i1 = (int)(g / ((size_t)N * N));
+  const double x1 = (i1 - N / 2) * a, x2 = (i2 - N / 2) * a, x3 = (i3 - N / 2) * a;
+  const double r = sqrt(x1 * x1 + x2 * x2 + x3 * x3);
+  double vr = 0.0, vi = 0.0;
+  switch (kind) {
+    case PV_HARMONIC: vr = 0.5 * p0 * r * r; break;
+    case PV_CORNELL: { const double rf = fmax(r, p2); vr = -p0 / rf + p1 * rf; } break;
+    case PV_COULOMB: { const double rf = fmax(r, p1); vr = -p0 / rf; } break;
+    case PV_SPLINE: vr = spline_eval(knots, nk, r); break;
+    default: break;
+  }
+  if (add) { vr += add[g].x; vi += add[g].y; }
+  if (vcomplex) { v64[2 * g] = vr; v64[2 * g + 1] = vi; }
+  else v64[g] = vr;
+}
+
+// state-precision V (FDTD), and e^{-dt V/2}, e^{-dt V} (FFT kinds) from the FP64 table
+template <typename T>
+__global__ void k_dt_tables(const double *v64, int vcomplex, size_t N3, double dt, void *vtab, void *hfac,
+                            void *h2fac, T *ktab, const double *ksym64, int N, int kin) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < (size_t)N && ktab) {
+    // separable symbols: e^{-dt t(k_j)}; relativistic: the lattice p^2 table itself
+    const double ks = ksym64[g];
+    ktab[g] = (T)(kin == KIN_REL ? ks : exp(-dt * ks));
+  }
+  if (g >= N3) return;
+  const double vr = vcomplex ? v64[2 * g] : v64[g];
+  const double vi = vcomplex ? v64[2 * g + 1] : 0.0;
+  if (vtab) {
+    if (vcomplex) ((C<T> *)vtab)[g] = mkc<T>((T)vr, (T)vi);
+    else ((T *)vtab)[g] = (T)vr;
+  }
+  if (hfac) {
+    const double e1 = exp(-0.5 * dt * vr), e2 = exp(-dt * vr);
+    if (vcomplex) {
+      double s1, c1, s2, c2;
+      sincos(0.5 * dt * vi, &s1, &c1);
+      sincos(dt * vi, &s2, &c2);
+      ((C<T> *)hfac)[g] = mkc<T>((T)(e1 * c1), (T)(-e1 * s1));
+      ((C<T> *)h2fac)[g] = mkc<T>((T)(e2 * c2), (T)(-e2 * s2));
+    } else {
+      ((T *)hfac)[g] = (T)e1;
+      ((T *)h2fac)[g] = (T)e2;
+    }
+  }
+}
+
+// --------------------------------------------------------------- stencil
+
+// psi' = A psi + B c (sum of 6 neighbours - 6 psi), c = dt/(2 m a^2),
+// A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2); walls are ghost zeros.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) k_stencil(const LaunchList L) {
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const int N = d.N;
+  const size_t N3 = (size_t)N * N * N;
+  const C<T> *src = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi);
+  C<T> *dst = (C<T> *)((mode & M_SWAP) ? d.psi : d.alt);
+  const T c = (T)d.stencil_c, hdt = (T)(0.5 * d.dt);
+  const long long base = (long long)(blockIdx.x - L.tile_start[e]) * RED_THREADS * EW_PER_THREAD;
+  const long long total = (long long)d.k * N3;
+#pragma unroll
+  for (int q = 0; q < EW_PER_THREAD; ++q) {
+    const long long gi = base + q * RED_THREADS + threadIdx.x;
+    if (gi >= total) break;
+    const size_t x = (size_t)(gi % N3);
+    const C<T> *sp = src + (gi - x);
+    const int i3 = (int)(x % N), i2 = (int)((x / N) % N), i1 = (int)(x / ((size_t)N * N));
+    const C<T> v = sp[x];
+    C<T> acc = cscale(v, (T)-6);
+    if (i3 > 0) acc = cadd(acc, sp[x - 1]);
+    if (i3 < N - 1) acc = cadd(acc, sp[x + 1]);
+    if (i2 > 0) acc = cadd(acc, sp[x - N]);
+    if (i2 < N - 1) acc = cadd(acc, sp[x + N]);
+    if (i1 > 0) acc = cadd(acc, sp[x - (size_t)N * N]);
+    if (i1 < N - 1) acc = cadd(acc, sp[x + (size_t)N * N]);
+    C<T> out;
+    if (d.vcomplex) {
+      const C<T> V = ((const C<T> *)d.vtab)[x];
+      // B = 1/(1 + dt V/2), A = (1 - dt V/2) B
+      const T dr = (T)1 + hdt * V.x, di = hdt * V.y;
+      const T den = (T)1 / (dr * dr + di * di);
+      const C<T> B = mkc<T>(dr * den, -di * den);
+      const C<T> A = cmul(mkc<T>((T)1 - hdt * V.x, -hdt * V.y), B);
+      out = cadd(cmul(A, v), cmul(B, cscale(acc, c)));
+    } else {
+      const T V = ((const T *)d.vtab)[x];
+      const T B = (T)1 / ((T)1 + hdt * V);
+      const T A = ((T)1 - hdt * V) * B;
+      out = cadd(cscale(v, A), cscale(acc, B * c));
+    }
+    dst[gi] = out;
+  }
+}
+
+// ---------------------------------------------------------------- parity
+
+// reflection of index i on axis: periodic (N - i) mod N; walled N - i (N = wall)
+__device__ __forceinline__ int mirror(int i, int N, bool periodic) {
+  const int m = N - i;
+  return periodic ? (m == N ? 0 : m) : m;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) k_parity(const LaunchList L) {
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const int N = d.N;
+  const size_t N3 = (size_t)N * N * N;
+  const C<T> *src = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi);
+  C<T> *dst = (C<T> *)((mode & M_SWAP) ? d.psi : d.alt);
+  const bool periodic = d.kin != KIN_FDTD;
+  const long long base = (long long)(blockIdx.x - L.tile_start[e]) * RED_THREADS * EW_PER_THREAD;
+  const long long total = (long long)d.k * N3;
+#pragma unroll
+  for (int q = 0; q < EW_PER_THREAD; ++q) {
+    const long long gi = base + q * RED_THREADS + threadIdx.x;
+    if (gi >= total) break;
+    const int s = (int)(gi / N3);
+    const size_t x = (size_t)(gi - (long long)s * N3);
+    const C<T> *sp = src + (size_t)s * N3;
+    const int i3 = (int)(x % N), i2 = (int)((x / N) % N), i1 = (int)(x / ((size_t)N * N));
+    const int sec = d.sector[s];
+    const C<T> v = sp[x];
+    if (sec == 0) { dst[gi] = v; continue; }
+    const int m1 = mirror(i1, N, periodic), m2 = mirror(i2, N, periodic), m3 = mirror(i3, N, periodic);
+    auto at = [&](int j1, int j2, int j3) -> C<T> {
+      if (j1 == N || j2 == N || j3 == N) return mkc<T>(0, 0);
+      return sp[((size_t)j1 * N + j2) * N + j3];
+    };
+    const C<T> all = at(m1, m2, m3);
+    C<T> out;
+    if (sec == 1) out = cscale(cadd(v, all), (T)0.5);
+    else if (sec == 2) out = cscale(csub(v, all), (T)0.5);
+    else {
+      // P^-_{p_k} = (1 + R_other)(1 - R_k)/4
+      C<T> r_oth, r_k;
+      if (sec == 3) { r_oth = at(i1, m2, m3); r_k = at(m1, i2, i3); }
+      else if (sec == 4) { r_oth = at(m1, i2, m3); r_k = at(i1, m2, i3); }
+      else { r_oth = at(m1, m2, i3); r_k = at(i1, i2, m3); }
+      out = cscale(csub(cadd(v, r_oth), cadd(r_k, all)), (T)0.25);
+    }
+    dst[gi] = out;
+  }
+}
+
+// ------------------------------------------------------------- reductions
+
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double *out) {
+  __shared__ double red[RED_THREADS / 64][NV > 0 ? NV : 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[w][q] = v;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < NV; q += blockDim.x) {
+    double v = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < RED_THREADS / 64; ++ww) v += red[ww][q];
+    out[q] = v;
+  }
+}
+
+// Gram partials G_ij = sum conj(psi_i) psi_j, i <= j, over one block's range of sites.
+template <typename T, int KS>
+__global__ void __launch_bounds__(RED_THREADS) k_gram(const LaunchList L) {
+  constexpr int NP = KS * (KS + 1) / 2;
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const int blk = blockIdx.x - L.tile_start[e];
+  const size_t N3 = (size_t)d.N * d.N * d.N;
+  const C<T> *src = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi);
+  const size_t chunk = (N3 + d.nblk_red - 1) / d.nblk_red;
+  const size_t lo = blk * chunk, hi = (lo + chunk < N3) ? lo + chunk : N3;
+  double acc[2 * NP];
+#pragma unroll
+  for (int q = 0; q < 2 * NP; ++q) acc[q] = 0.0;
+  for (size_t x = lo + threadIdx.x; x < hi; x += RED_THREADS) {
+    double2 v[KS];
+#pragma unroll
+    for (int i = 0; i < KS; ++i) {
+      const C<T> u = src[(size_t)i * N3 + x];
+      v[i] = make_double2((double)u.x, (double)u.y);
+    }
+    int p = 0;
+#pragma unroll
+    for (int i = 0; i < KS; ++i)
+#pragma unroll
+      for (int j = i; j < KS; ++j, ++p) {
+        acc[2 * p] += v[i].x * v[j].x + v[i].y * v[j].y;
+        acc[2 * p + 1] += v[i].x * v[j].y - v[i].y * v[j].x;
+      }
+  }
+  block_reduce_store<2 * NP>(acc, d.partials + (size_t)blk * (2 * MAX_PAIRS));
+}
+
+__device__ __forceinline__ int pair_index(int i, int j, int KS) { return i * KS - i * (i - 1) / 2 + (j - i); }
+
+// Sum the partials (fixed order), Cholesky G = R^H R per sector, coef = R^{-1}.
+__global__ void __launch_bounds__(RED_THREADS) k_gram_finalize(const LaunchList L) {
+  const int e = blockIdx.x;
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const int KS = d.k;
+  const int NP = KS * (KS + 1) / 2;
+  __shared__ double G[MAX_PAIRS * 2];
+  for (int q = threadIdx.x; q < 2 * NP; q += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < d.nblk_red; ++b) s += d.partials[(size_t)b * (2 * MAX_PAIRS) + q];
+    G[q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double Rr[MAX_STATES][MAX_STATES], Ri[MAX_STATES][MAX_STATES];
+  double Xr[MAX_STATES][MAX_STATES], Xi[MAX_STATES][MAX_STATES];
+  for (int i = 0; i < MAX_STATES; ++i)
+    for (int j = 0; j < MAX_STATES; ++j) { Rr[i][j] = Ri[i][j] = Xr[i][j] = Xi[i][j] = 0.0; }
+  int bad = 0;
+  bool done[MAX_STATES] = {false, false, false, false, false, false, false, false};
+  for (int first = 0; first < KS; ++first) {
+    if (done[first]) continue;
+    int idx[MAX_STATES], n = 0;
+    for (int s = first; s < KS; ++s)
+      if (d.sector[s] == d.sector[first]) { idx[n++] = s; done[s] = true; }
+    for (int jj = 0; jj < n; ++jj) {
+      const int j = idx[jj];
+      for (int ii = 0; ii < jj; ++ii) {
+        const int i = idx[ii];
+        const int p = pair_index(i, j, KS);
+        double sr = G[2 * p], si = G[2 * p + 1];
+        for (int ll = 0; ll < ii; ++ll) {
+          const int l = idx[ll];
+          // conj(R_li) R_lj
+          sr -= Rr[l][i] * Rr[l][j] + Ri[l][i] * Ri[l][j];
+          si -= Rr[l][i] * Ri[l][j] - Ri[l][i] * Rr[l][j];
+        }
+        Rr[i][j] = sr / Rr[i][i];
+        Ri[i][j] = si / Rr[i][i];
+      }
+      const int p = pair_index(j, j, KS);
+      double dd = G[2 * p];
+      const double gjj = dd;
+      for (int ll = 0; ll < jj; ++ll) {
+        const int l = idx[ll];
+        dd -= Rr[l][j] * Rr[l][j] + Ri[l][j] * Ri[l][j];
+      }
+      if (!(gjj > 0.0) || !isfinite(gjj) || !(dd > 1e-24 * gjj) || !isfinite(dd)) { bad = 1; dd = 1.0; }
+      Rr[j][j] = sqrt(dd);
+      Ri[j][j] = 0.0;
+    }
+    // X = R^{-1} (upper triangular within the sector)
+    for (int jj = 0; jj < n; ++jj) {
+      const int j = idx[jj];
+      Xr[j][j] = 1.0 / Rr[j][j];
+      for (int ii = jj - 1; ii >= 0; --ii) {
+        const int i = idx[ii];
+        double sr = 0.0, si = 0.0;
+        for (int ll = ii + 1; ll <= jj; ++ll) {
+          const int l = idx[ll];
+          sr += Rr[i][l] * Xr[l][j] - Ri[i][l] * Xi[l][j];
+          si += Rr[i][l] * Xi[l][j] + Ri[i][l] * Xr[l][j];
+        }
+        Xr[i][j] = -sr / Rr[i][i];
+        Xi[i][j] = -si / Rr[i][i];
+      }
+    }
+  }
+  for (int i = 0; i < KS; ++i)
+    for (int j = 0; j < KS; ++j) {
+      d.coef[(i * MAX_STATES + j) * 2] = Xr[i][j];
+      d.coef[(i * MAX_STATES + j) * 2 + 1] = Xi[i][j];
+    }
+  if (bad) d.energy[2 * MAX_STATES] = 1.0;
+}
+
+// psi_j <- sum_{i <= j} src_i coef_ij  (in place when src is psi)
+template <typename T, int KS>
+__global__ void __launch_bounds__(RED_THREADS) k_apply(const LaunchList L) {
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const size_t N3 = (size_t)d.N * d.N * d.N;
+  const C<T> *src = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi);
+  C<T> *dst = (C<T> *)d.psi;
+  C<T> cf[KS][KS];
+#pragma unroll
+  for (int i = 0; i < KS; ++i)
+#pragma unroll
+    for (int j = 0; j < KS; ++j)
+      cf[i][j] = mkc<T>((T)d.coef[(i * MAX_STATES + j) * 2], (T)d.coef[(i * MAX_STATES + j) * 2 + 1]);
+  const long long base = (long long)(blockIdx.x - L.tile_start[e]) * RED_THREADS * EW_PER_THREAD;
+#pragma unroll
+  for (int q = 0; q < EW_PER_THREAD; ++q) {
+    const long long x = base + q * RED_THREADS + threadIdx.x;
+    if (x >= (long long)N3) break;
+    C<T> v[KS];
+#pragma unroll
+    for (int i = 0; i < KS; ++i) v[i] = src[(size_t)i * N3 + x];
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      C<T> o = mkc<T>(0, 0);
+#pragma unroll
+      for (int i = 0; i <= j; ++i) o = cadd(o, cmul(v[i], cf[i][j]));
+      dst[(size_t)j * N3 + x] = o;
+    }
+  }
+}
+
+// ------------------------------------------------------------- energies
+
+// per state: |psi|^2, V |psi|^2 (re, im) and, for H_K^(0), conj(psi) H_K psi (re, im)
+template <typename T, int KS>
+__global__ void __launch_bounds__(RED_THREADS) k_energy_partials(const LaunchList L) {
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const int blk = blockIdx.x - L.tile_start[e];
+  const int N = d.N;
+  const size_t N3 = (size_t)N * N * N;
+  const C<T> *src = (const C<T> *)d.psi;
+  const size_t chunk = (N3 + d.nblk_red - 1) / d.nblk_red;
+  const size_t lo = blk * chunk, hi = (lo + chunk < N3) ? lo + chunk : N3;
+  const bool fdtd = d.kin == KIN_FDTD;
+  const double kc = 1.0 / (2.0 * d.m * d.a * d.a);
+  double acc[5 * KS];
+#pragma unroll
+  for (int q = 0; q < 5 * KS; ++q) acc[q] = 0.0;
+  for (size_t x = lo + threadIdx.x; x < hi; x += RED_THREADS) {
+    double vr, vi = 0.0;
+    if (d.vcomplex) { vr = d.v64[2 * x]; vi = d.v64[2 * x + 1]; }
+    else vr = d.v64[x];
+    const int i3 = (int)(x % N), i2 = (int)((x / N) % N), i1 = (int)(x / ((size_t)N * N));
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const C<T> *sp = src + (size_t)s * N3;
+      const C<T> u = sp[x];
+      const double ur = u.x, ui = u.y;
+      const double n2 = ur * ur + ui * ui;
+      acc[5 * s] += n2;
+      acc[5 * s + 1] += vr * n2;
+      acc[5 * s + 2] += vi * n2;
+      if (fdtd) {
+        double lr = -6.0 * ur, li = -6.0 * ui;
+        C<T> w;
+        if (i3 > 0) { w = sp[x - 1]; lr += w.x; li += w.y; }
+        if (i3 < N - 1) { w = sp[x + 1]; lr += w.x; li += w.y; }
+        if (i2 > 0) { w = sp[x - N]; lr += w.x; li += w.y; }
+        if (i2 < N - 1) { w = sp[x + N]; lr += w.x; li += w.y; }
+        if (i1 > 0) { w = sp[x - (size_t)N * N]; lr += w.x; li += w.y; }
+        if (i1 < N - 1) { w = sp[x + (size_t)N * N]; lr += w.x; li += w.y; }
+        // conj(u) * (-L u) / (2 m a^2)
+        acc[5 * s + 3] += -kc * (ur * lr + ui * li);
+        acc[5 * s + 4] += -kc * (ur * li - ui * lr);
+      }
+    }
+  }
+  block_reduce_store<5 * KS>(acc, d.partials + (size_t)blk * (2 * MAX_PAIRS));
+}
+
+// state precision -> FP64 copy of all states (input of the FP64 energy transform)
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) k_to64(const LaunchList L) {
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const long long total = (long long)d.k * d.N * d.N * d.N;
+  const long long base = (long long)(blockIdx.x - L.tile_start[e]) * RED_THREADS * EW_PER_THREAD;
+  const C<T> *src = (const C<T> *)d.psi;
+#pragma unroll
+  for (int q = 0; q < EW_PER_THREAD; ++q) {
+    const long long gi = base + q * RED_THREADS + threadIdx.x;
+    if (gi >= total) break;
+    const C<T> u = src[gi];
+    d.scratch64[gi] = make_double2((double)u.x, (double)u.y);
+  }
+}
+
+// sum_k T(k) |psi^(k)|^2 / N^3 per state, from the FP64 forward transform in scratch64
+template <int KS>
+__global__ void __launch_bounds__(RED_THREADS) k_kin_partials(const LaunchList L) {
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const int blk = blockIdx.x - L.tile_start[e];
+  const int N = d.N;
+  const size_t N3 = (size_t)N * N * N;
+  const size_t chunk = (N3 + d.nblk_red - 1) / d.nblk_red;
+  const size_t lo = blk * chunk, hi = (lo + chunk < N3) ? lo + chunk : N3;
+  const double m = d.m;
+  double acc[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) acc[s] = 0.0;
+  for (size_t x = lo + threadIdx.x; x < hi; x += RED_THREADS) {
+    const int i3 = (int)(x % N), i2 = (int)((x / N) % N), i1 = (int)(x / ((size_t)N * N));
+    const double ks = d.ksym64[i1] + d.ksym64[i2] + d.ksym64[i3];
+    const double tk = (d.kin == KIN_REL) ? ks / (sqrt(ks + m * m) + m) : ks;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const double2 u = d.scratch64[(size_t)s * N3 + x];
+      acc[s] += tk * (u.x * u.x + u.y * u.y);
+    }
+  }
+  block_reduce_store<KS>(acc, d.partials + (size_t)(d.nblk_red + blk) * (2 * MAX_PAIRS));
+}
+
+// E_s = (<V> + <H_K>)/<psi|psi>; aux = trace slot (or -1)
+__global__ void __launch_bounds__(RED_THREADS) k_energy_finalize(const LaunchList L) {
+  const int e = blockIdx.x;
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const int KS = d.k;
+  const bool fdtd = d.kin == KIN_FDTD;
+  __shared__ double S[6 * MAX_STATES];
+  for (int q = threadIdx.x; q < 6 * KS; q += blockDim.x) {
+    double s = 0.0;
+    if (q < 5 * KS) {
+      for (int b = 0; b < d.nblk_red; ++b) s += d.partials[(size_t)b * (2 * MAX_PAIRS) + q];
+    } else if (!fdtd) {
+      const int st = q - 5 * KS;
+      for (int b = 0; b < d.nblk_red; ++b) s += d.partials[(size_t)(d.nblk_red + b) * (2 * MAX_PAIRS) + st];
+    }
+    S[q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const int slot = L.aux[e];
+  for (int s = 0; s < KS; ++s) {
+    const double nrm = S[5 * s];
+    double er = S[5 * s + 1], ei = S[5 * s + 2];
+    if (fdtd) { er += S[5 * s + 3]; ei += S[5 * s + 4]; }
+    else er += S[5 * KS + s] * d.inv_n3;
+    er /= nrm;
+    ei /= nrm;
+    d.energy[2 * s] = er;
+    d.energy[2 * s + 1] = ei;
+    if (slot >= 0 && d.trace) {
+      d.trace[((size_t)slot * KS + s) * 2] = er;
+      d.trace[((size_t)slot * KS + s) * 2 + 1] = ei;
+    }
+    if (!isfinite(er) || !isfinite(ei) || !(nrm > 0.0)) d.energy[2 * MAX_STATES] = 1.0;
+  }
+}
+
+// host <-> state conversions through an FP64 staging buffer
+template <typename T>
+__global__ void k_from64_slot(C<T> *dst, const double2 *src, size_t n) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) dst[g] = mkc<T>((T)src[g].x, (T)src[g].y);
+}
+template <typename T>
+__global__ void k_to64_slot(double2 *dst, const C<T> *src, size_t n) {
+  const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) dst[g] = make_double2((double)src[g].x, (double)src[g].y);
+}
+
+// ------------------------------------------------------------- launchers
+
+template <typename T>
+void launch_tables_t(void *tw, double2 *tw64, double *ksym64, int N, int kin, double a, double m, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles<T>, dim3((N + 255) / 256), dim3(256), 0, st, (C<T> *)tw, tw64, ksym64, N, kin, a, m);
+}
+void launch_tables(bool dbl, void *tw, double2 *tw64, double *ksym64, int N, int kin, double a, double m, hipStream_t st) {
+  if (dbl) launch_tables_t<double>(tw, tw64, ksym64, N, kin, a, m, st);
+  else launch_tables_t<float>(tw, tw64, ksym64, N, kin, a, m, st);
+}
+void launch_potential(double *v64, int vcomplex, int N, double a, int kind, const double *p, const double *knots, int nk,
+                      const double2 *add, hipStream_t st) {
+  const size_t N3 = (size_t)N * N * N;
+  hipLaunchKernelGGL(k_potential, dim3((unsigned)((N3 + 255) / 256)), dim3(256), 0, st, v64, vcomplex, N, a, kind, p[0],
+                     p[1], p[2], knots, nk, add);
+}
+void launch_dt_tables(bool dbl, const double *v64, int vcomplex, int N, double dt, void *vtab, void *hfac, void *h2fac,
+                      void *ktab, const double *ksym64, int kin, hipStream_t st) {
+  const size_t N3 = (size_t)N * N * N;
+  const size_t n = N3 > (size_t)N ? N3 : (size_t)N;
+  if (dbl)
+    hipLaunchKernelGGL(k_dt_tables<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v64, vcomplex, N3, dt,
+                       vtab, hfac, h2fac, (double *)ktab, ksym64, N, kin);
+  else
+    hipLaunchKernelGGL(k_dt_tables<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v64, vcomplex, N3, dt,
+                       vtab, hfac, h2fac, (float *)ktab, ksym64, N, kin);
+}
+void launch_from64_slot(bool dbl, void *dst, const double2 *src, size_t n, hipStream_t st) {
+  if (dbl) hipLaunchKernelGGL(k_from64_slot<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (double2 *)dst, src, n);
+  else hipLaunchKernelGGL(k_from64_slot<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (float2 *)dst, src, n);
+}
+void launch_to64_slot(bool dbl, double2 *dst, const void *src, size_t n, hipStream_t st) {
+  if (dbl) hipLaunchKernelGGL(k_to64_slot<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, (const double2 *)src, n);
+  else hipLaunchKernelGGL(k_to64_slot<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst, (const float2 *)src, n);
+}
+
+int ew_tiles_host(long long n) { return ew_tiles(n); }
+
+void launch_stencil(const LaunchList &L, int total, bool dbl, hipStream_t st) {
+  if (dbl) hipLaunchKernelGGL(k_stencil<double>, dim3(total), dim3(RED_THREADS), 0, st, L);
+  else hipLaunchKernelGGL(k_stencil<float>, dim3(total), dim3(RED_THREADS), 0, st, L);
+}
+void launch_parity(const LaunchList &L, int total, bool dbl, hipStream_t st) {
+  if (dbl) hipLaunchKernelGGL(k_parity<double>, dim3(total), dim3(RED_THREADS), 0, st, L);
+  else hipLaunchKernelGGL(k_parity<float>, dim3(total), dim3(RED_THREADS), 0, st, L);
+}
+void launch_to64(const LaunchList &L, int total, bool dbl, hipStream_t st) {
+  if (dbl) hipLaunchKernelGGL(k_to64<double>, dim3(total), dim3(RED_THREADS), 0, st, L);
+  else hipLaunchKernelGGL(k_to64<float>, dim3(total), dim3(RED_THREADS), 0, st, L);
+}
+
+#define QF_KS_SWITCH(KS, MACRO) \
+  switch (KS) {                 \
+    case 1: MACRO(1); break;    \
+    case 2: MACRO(2); break;    \
+    case 3: MACRO(3); break;    \
+    case 4: MACRO(4); break;    \
+    case 5: MACRO(5); break;    \
+    case 6: MACRO(6); break;    \
+    case 7: MACRO(7); break;    \
+    default: MACRO(8); break;   \
+  }
+
+void launch_gram(const LaunchList &L, int total, int KS, bool dbl, hipStream_t st) {
+#define G_(K)                                                                                  \
+  if (dbl) hipLaunchKernelGGL((k_gram<double, K>), dim3(total), dim3(RED_THREADS), 0, st, L); \
+  else hipLaunchKernelGGL((k_gram<float, K>), dim3(total), dim3(RED_THREADS), 0, st, L);
+  QF_KS_SWITCH(KS, G_)
+#undef G_
+}
+void launch_apply(const LaunchList &L, int total, int KS, bool dbl, hipStream_t st) {
+#define A_(K)                                                                                   \
+  if (dbl) hipLaunchKernelGGL((k_apply<double, K>), dim3(total), dim3(RED_THREADS), 0, st, L); \
+  else hipLaunchKernelGGL((k_apply<float, K>), dim3(total), dim3(RED_THREADS), 0, st, L);
+  QF_KS_SWITCH(KS, A_)
+#undef A_
+}
+void launch_energy_partials(const LaunchList &L, int total, int KS, bool dbl, hipStream_t st) {
+#define E_(K)                                                                                             \
+  if (dbl) hipLaunchKernelGGL((k_energy_partials<double, K>), dim3(total), dim3(RED_THREADS), 0, st, L); \
+  else hipLaunchKernelGGL((k_energy_partials<float, K>), dim3(total), dim3(RED_THREADS), 0, st, L);
+  QF_KS_SWITCH(KS, E_)
+#undef E_
+}
+void launch_kin_partials(const LaunchList &L, int total, int KS, hipStream_t st) {
+#define K_(K) hipLaunchKernelGGL((k_kin_partials<K>), dim3(total), dim3(RED_THREADS), 0, st, L);
+  QF_KS_SWITCH(KS, K_)
+#undef K_
+}
+void launch_gram_finalize(const LaunchList &L, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_finalize, dim3(L.n), dim3(RED_THREADS), 0, st, L);
+}
+void launch_energy_finalize(const LaunchList &L, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_finalize, dim3(L.n), dim3(RED_THREADS), 0, st, L);
+}
+
+}  // namespace qf

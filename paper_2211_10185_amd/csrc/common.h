@@ -1,0 +1,117 @@
+// Shared device/host definitions of the gfx950 imaginary-time solver.
+//
+// Data layout in HBM (one solve, "member"):
+//   psi   [k][N][N][N] interleaved complex (float2 for complex64 states,
+//         double2 for complex128), x3 fastest: site (i1,i2,i3) of state s at
+//         s*N^3 + (i1*N + i2)*N + i3.
+//   alt   same shape; ping-pong target of the FDTD stencil and of the parity
+//         projection (allocated only when needed).
+//   vtab  V in the state precision, real [N^3] or complex [N^3].
+//   hfac  e^{-dt V/2}, h2fac e^{-dt V}: same type as vtab (FFT kinds).
+//   ktab  [N] per-axis kinetic table in the state precision: e^{-dt t(k_j)}
+//         for the separable symbols of eqs. (HK1)/(HK2), 4 sin^2(k_j/2)/a^2 for
+//         eq. (HK3).
+//   tw    [N] roots of unity e^{-2 pi i m/N} in the state precision.
+//   tw64, ksym64: FP64 copies used by the FP64 energy measurement.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qf {
+
+template <typename T> struct CT;
+template <> struct CT<float> { using type = float2; };
+template <> struct CT<double> { using type = double2; };
+template <typename T> using C = typename CT<T>::type;
+
+template <typename T> __host__ __device__ __forceinline__ C<T> mkc(T x, T y) { C<T> r; r.x = x; r.y = y; return r; }
+template <typename V> __host__ __device__ __forceinline__ V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename V> __host__ __device__ __forceinline__ V csub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename V> __host__ __device__ __forceinline__ V cmul(V a, V b) {
+  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+template <typename V, typename S> __host__ __device__ __forceinline__ V cscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename V> __host__ __device__ __forceinline__ V mul_mi(V a) {
+  V r;
+  if (INV) { r.x = -a.y; r.y = a.x; } else { r.x = a.y; r.y = -a.x; }
+  return r;
+}
+
+constexpr int MAX_STAGES = 12;
+constexpr int MAX_STATES = 8;
+constexpr int MAX_PAIRS = MAX_STATES * (MAX_STATES + 1) / 2;
+constexpr int MAX_LAUNCH = 64;       // members per launch list
+
+// Kinetic kinds (eqs. HK0..HK3)
+enum { KIN_FDTD = 0, KIN_P2 = 1, KIN_SIN2 = 2, KIN_REL = 3 };
+
+// Mode bits of a real-space (plane or row) pass and of a column pass.
+enum : uint32_t {
+  M_PRE = 1u,    // x h before the forward transform (chunk start)
+  M_INV = 2u,    // inverse transform first
+  M_MID = 4u,    // x h^2 between inverse and forward (steady state)
+  M_FWD = 8u,    // forward transform
+  M_POST = 16u,  // x h after the inverse transform (chunk end)
+  M_KIN = 32u,   // column pass: x e^{-dt T(k)}/N^3 between forward and inverse
+  M_AXIS1 = 64u, // column pass along x1 (else x2)
+  M_SWAP = 128u, // stencil: read alt, write psi (else read psi, write alt)
+  M_SCALE = 256u // column pass: x 1/N^3 after the last transform
+};
+
+// Everything a kernel needs to know about one member (one solve).  Lives in
+// device memory; kernels index it through a launch list.
+struct PassDesc {
+  void *psi;
+  void *alt;
+  const void *vtab;
+  const void *hfac;
+  const void *h2fac;
+  const void *ktab;
+  const void *tw;
+  const void *tw64;
+  const double *ksym64;   // [N] t(k_j) (HK1/HK2) or 4 sin^2(k_j/2)/a^2 (HK3), FP64
+  const double *v64;      // [N^3] V in FP64, real or (re, im) interleaved
+  double2 *scratch64;     // [k][N^3] FP64 copy for the energy transform
+  double *partials;       // [2][nblk_red][MAX_PAIRS][2] FP64 reduction partials
+  double *coef;           // [MAX_STATES][MAX_STATES][2] FP64 orthonormalisation coefficients
+  double *energy;         // [MAX_STATES][2] last energies; [2*MAX_STATES] status word
+  double *trace;          // [cap][k][2] energy trace (or null)
+  int32_t N, k, kin, vcomplex;
+  int32_t nst;
+  int32_t radix[MAX_STAGES];
+  int32_t sector[MAX_STATES];
+  int32_t nblk_red;       // reduction blocks per state sweep
+  int32_t pad0;
+  double a, m, dt;
+  double stencil_c;       // dt / (2 m a^2)
+  double inv_n3;
+};
+
+// One launch: which members take part, with which mode, and where their tiles
+// start in the flattened grid.  Passed by value (kernel arguments), so it is
+// captured as-is by a HIP graph.
+struct LaunchList {
+  int32_t n;
+  int32_t tile_start[MAX_LAUNCH + 1];
+  const void *descp[MAX_LAUNCH];   // device PassDesc of each entry
+  uint16_t mode[MAX_LAUNCH];
+  int32_t aux[MAX_LAUNCH];         // per-entry extra (trace slot, ...)
+};
+
+__device__ __forceinline__ int find_entry(const LaunchList &L, int blk) {
+  int lo = 0, hi = L.n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (L.tile_start[mid] <= blk) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Threads per block of each kernel family.
+constexpr int PLANE_THREADS = 1024;
+constexpr int LINE_THREADS = 256;
+constexpr int RED_THREADS = 256;
+
+}  // namespace qf

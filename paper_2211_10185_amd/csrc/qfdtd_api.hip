@@ -1,0 +1,927 @@
+// C ABI of the solver: context lifecycle, the per-chunk pass schedule, the
+// measurement (orthonormalisation and FP64 energies) and launch timing.
+//
+// Schedules (per member; k states are carried together through every pass):
+//   FFT kinds, plane fits LDS (complex64 N <= 128, complex128 N <= 96):
+//     chunk of n steps = plane[h, F23] ; { col1[F1, e^{-dt T}, F1^-1] ; plane[F23^-1, h^2, F23] } x (n-1)
+//                        ; col1[...] ; plane[F23^-1, h]                 -> 2n + 1 passes
+//   FFT kinds, larger N:
+//     row[h, F3] ; col2[F2] ; { col1[...] ; col2[F2^-1] ; row[F3^-1, h^2, F3] ; col2[F2] } x (n-1)
+//                        ; col1[...] ; col2[F2^-1] ; row[F3^-1, h]       -> 4n + 1 passes
+//   H_K^(0): n stencil passes (ping-pong between psi and alt).
+// After every chunk: parity projection (if any sector is set), FP64 Gram
+// matrix, Cholesky per sector, psi <- psi R^{-1}.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "qfdtd.h"
+
+namespace qf {
+size_t plane_lds(int N, bool dbl);
+size_t row_lds(int N, bool dbl);
+size_t col_lds(int N, bool dbl);
+int plane_tiles(int N, int k);
+int row_tiles(int N, int k);
+int col_tiles(int N, int k, bool dbl);
+hipError_t fft_kernels_init();
+void launch_plane(const LaunchList &L, int total, size_t lds, bool dbl, hipStream_t st);
+void launch_row(const LaunchList &L, int total, size_t lds, bool dbl, hipStream_t st);
+void launch_col(const LaunchList &L, int total, size_t lds, bool dbl, hipStream_t st);
+void launch_tables(bool dbl, void *tw, double2 *tw64, double *ksym64, int N, int kin, double a, double m, hipStream_t st);
+void launch_potential(double *v64, int vcomplex, int N, double a, int kind, const double *p, const double *knots, int nk,
+                      const double2 *add, hipStream_t st);
+void launch_dt_tables(bool dbl, const double *v64, int vcomplex, int N, double dt, void *vtab, void *hfac, void *h2fac,
+                      void *ktab, const double *ksym64, int kin, hipStream_t st);
+void launch_from64_slot(bool dbl, void *dst, const double2 *src, size_t n, hipStream_t st);
+void launch_to64_slot(bool dbl, double2 *dst, const void *src, size_t n, hipStream_t st);
+int ew_tiles_host(long long n);
+void launch_stencil(const LaunchList &L, int total, bool dbl, hipStream_t st);
+void launch_parity(const LaunchList &L, int total, bool dbl, hipStream_t st);
+void launch_to64(const LaunchList &L, int total, bool dbl, hipStream_t st);
+void launch_gram(const LaunchList &L, int total, int KS, bool dbl, hipStream_t st);
+void launch_apply(const LaunchList &L, int total, int KS, bool dbl, hipStream_t st);
+void launch_energy_partials(const LaunchList &L, int total, int KS, bool dbl, hipStream_t st);
+void launch_kin_partials(const LaunchList &L, int total, int KS, hipStream_t st);
+void launch_gram_finalize(const LaunchList &L, hipStream_t st);
+void launch_energy_finalize(const LaunchList &L, hipStream_t st);
+}  // namespace qf
+
+using namespace qf;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+enum { TC_PLANE = 0, TC_ROW = 1, TC_COL = 2, TC_STENCIL = 3, TC_MEAS = 4, TC_N = 5 };
+
+struct Timer {
+  int every = 0;
+  long long seen[TC_N] = {0, 0, 0, 0, 0};
+  struct Rec { hipEvent_t a, b; int cls; double bytes; };
+  std::vector<Rec> pool;
+  size_t used = 0;
+  long long count[TC_N] = {0, 0, 0, 0, 0};
+  double sum_ms[TC_N] = {0, 0, 0, 0, 0};
+  double sum_bytes[TC_N] = {0, 0, 0, 0, 0};
+};
+
+bool smooth235(int n) {
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+int make_plan(int N, int32_t *radix) {
+  int n = N, s = 0;
+  while (n % 8 == 0 && n / 8 >= 2) { radix[s++] = 8; n /= 8; }
+  while (n % 4 == 0) { radix[s++] = 4; n /= 4; }
+  while (n % 8 == 0) { radix[s++] = 8; n /= 8; }
+  while (n % 2 == 0) { radix[s++] = 2; n /= 2; }
+  while (n % 5 == 0) { radix[s++] = 5; n /= 5; }
+  while (n % 3 == 0) { radix[s++] = 3; n /= 3; }
+  return s;
+}
+
+}  // namespace
+
+struct qfdtd_ctx {
+  int N = 0, kin = 0, prec = 0, k = 0, K = 50;
+  double a = 0, m = 0;
+  int sectors[MAX_STATES] = {0};
+  bool any_parity = false, vcomplex = false, dbl = false, plane = false, plane64 = false;
+  hipStream_t st = nullptr;
+  qfdtd_alloc_fn af = nullptr;
+  qfdtd_free_fn ff = nullptr;
+  void *au = nullptr;
+  std::string err;
+  std::vector<void *> allocs;
+  void *psi = nullptr, *alt = nullptr, *vtab = nullptr, *hfac = nullptr, *h2fac = nullptr, *ktab = nullptr, *tw = nullptr;
+  double2 *tw64 = nullptr, *scratch64 = nullptr;
+  double *ksym64 = nullptr, *v64 = nullptr, *partials = nullptr, *coef = nullptr, *energy = nullptr, *trace = nullptr;
+  PassDesc *d_desc = nullptr;   // [0] main (state precision), [1] FP64 measurement copy
+  PassDesc hd[2];
+  int nblk_red = 1;
+  double cur_dt = -1.0;
+  bool fresh = true;
+  uint32_t set_mask = 0;
+  bool poisoned = false;
+  int cur = 0;                  // H_K^(0): 1 when the state sits in alt
+  int trace_on = 0;
+  int64_t trace_cap = 0, trace_n = 0;
+  double *h_status = nullptr;   // pinned
+  hipEvent_t status_ev = nullptr;
+  bool status_pending = false;
+  Timer timer;
+
+  size_t n3() const { return (size_t)N * N * N; }
+  size_t csz() const { return dbl ? 16 : 8; }
+  size_t rsz() const { return dbl ? 8 : 4; }
+  bool fft() const { return kin != KIN_FDTD; }
+};
+
+namespace {
+
+void *dalloc(qfdtd_ctx *c, size_t bytes) {
+  void *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (c->af) p = c->af(bytes, c->au);
+  else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  if (p) c->allocs.push_back(p);
+  return p;
+}
+
+void free_all(qfdtd_ctx *c) {
+  for (void *p : c->allocs) {
+    if (c->ff) c->ff(p, c->au);
+    else (void)hipFree(p);
+  }
+  c->allocs.clear();
+}
+
+qfdtd_status fail(qfdtd_ctx *c, qfdtd_status s, const std::string &msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return s;
+}
+
+#define QF_HIP(c, call)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail(c, QFDTD_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+#define QF_LAUNCHED(c)                                                                           \
+  do {                                                                                           \
+    hipError_t e_ = hipGetLastError();                                                           \
+    if (e_ != hipSuccess) return fail(c, QFDTD_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------- timing
+
+int tbegin(qfdtd_ctx *c, int cls, double bytes) {
+  Timer &t = c->timer;
+  if (t.every <= 0) return -1;
+  if ((t.seen[cls]++ % t.every) != 0) return -1;
+  if (t.used == t.pool.size()) {
+    if (t.pool.size() >= 8192) return -1;
+    Timer::Rec r;
+    if (hipEventCreate(&r.a) != hipSuccess) return -1;
+    if (hipEventCreate(&r.b) != hipSuccess) { (void)hipEventDestroy(r.a); return -1; }
+    t.pool.push_back(r);
+  }
+  Timer::Rec &r = t.pool[t.used];
+  r.cls = cls;
+  r.bytes = bytes;
+  (void)hipEventRecord(r.a, c->st);
+  return (int)t.used++;
+}
+
+void tend(qfdtd_ctx *c, int idx) {
+  if (idx < 0) return;
+  (void)hipEventRecord(c->timer.pool[idx].b, c->st);
+}
+
+void tcollect(qfdtd_ctx *c) {
+  Timer &t = c->timer;
+  for (size_t i = 0; i < t.used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.pool[i].a, t.pool[i].b) == hipSuccess) {
+      t.count[t.pool[i].cls] += 1;
+      t.sum_ms[t.pool[i].cls] += ms;
+      t.sum_bytes[t.pool[i].cls] += t.pool[i].bytes;
+    }
+  }
+  t.used = 0;
+}
+
+// ------------------------------------------------------------- launch lists
+
+struct Entry {
+  qfdtd_ctx *c;
+  int which;        // 0 main desc, 1 FP64 measurement desc
+  uint32_t mode;
+  int tiles;
+  int aux;
+};
+
+enum Fam { F_PLANE, F_ROW, F_COL, F_STENCIL, F_PARITY, F_TO64, F_GRAM, F_APPLY, F_EPART, F_KPART, F_GFIN, F_EFIN };
+
+// algorithmic bytes moved by one member's share of a launch (for timing)
+double entry_bytes(const Entry &e, Fam f) {
+  const qfdtd_ctx *c = e.c;
+  const double n = (double)c->k * c->n3();
+  const double s = e.which ? 16.0 : (double)c->csz();
+  const double fsz = (c->vcomplex ? 2.0 : 1.0) * (e.which ? 8.0 : (double)c->rsz());
+  switch (f) {
+    case F_PLANE:
+    case F_ROW: return n * (2 * s + ((e.mode & (M_PRE | M_MID | M_POST)) ? fsz : 0.0));
+    case F_COL: return n * 2 * s;
+    case F_STENCIL: return n * (2 * s + fsz);
+    default: return n * 2 * s;
+  }
+}
+
+qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS = 0) {
+  if (es.empty()) return QFDTD_OK;
+  qfdtd_ctx *c0 = es[0].c;
+  hipStream_t st = c0->st;
+  for (size_t base = 0; base < es.size(); base += MAX_LAUNCH) {
+    LaunchList L;
+    std::memset(&L, 0, sizeof(L));
+    const size_t cnt = (es.size() - base) < (size_t)MAX_LAUNCH ? es.size() - base : MAX_LAUNCH;
+    int total = 0;
+    size_t lds = 0;
+    double bytes = 0;
+    for (size_t i = 0; i < cnt; ++i) {
+      const Entry &e = es[base + i];
+      L.tile_start[i] = total;
+      L.descp[i] = (const void *)(e.c->d_desc + e.which);
+      L.mode[i] = (uint16_t)e.mode;
+      L.aux[i] = e.aux;
+      total += e.tiles;
+      const int N = e.c->N;
+      size_t l = 0;
+      if (f == F_PLANE) l = plane_lds(N, dbl);
+      else if (f == F_ROW) l = row_lds(N, dbl);
+      else if (f == F_COL) l = col_lds(N, dbl);
+      if (l > lds) lds = l;
+      bytes += entry_bytes(e, f);
+    }
+    L.n = (int)cnt;
+    L.tile_start[cnt] = total;
+    int cls = -1;
+    if (f == F_PLANE) cls = TC_PLANE;
+    else if (f == F_ROW) cls = TC_ROW;
+    else if (f == F_COL) cls = TC_COL;
+    else if (f == F_STENCIL) cls = TC_STENCIL;
+    const int tix = cls >= 0 ? tbegin(c0, cls, bytes) : -1;
+    switch (f) {
+      case F_PLANE: launch_plane(L, total, lds, dbl, st); break;
+      case F_ROW: launch_row(L, total, lds, dbl, st); break;
+      case F_COL: launch_col(L, total, lds, dbl, st); break;
+      case F_STENCIL: launch_stencil(L, total, dbl, st); break;
+      case F_PARITY: launch_parity(L, total, dbl, st); break;
+      case F_TO64: launch_to64(L, total, dbl, st); break;
+      case F_GRAM: launch_gram(L, total, KS, dbl, st); break;
+      case F_APPLY: launch_apply(L, total, KS, dbl, st); break;
+      case F_EPART: launch_energy_partials(L, total, KS, dbl, st); break;
+      case F_KPART: launch_kin_partials(L, total, KS, st); break;
+      case F_GFIN: launch_gram_finalize(L, st); break;
+      case F_EFIN: launch_energy_finalize(L, st); break;
+    }
+    tend(c0, tix);
+    QF_LAUNCHED(c0);
+  }
+  return QFDTD_OK;
+}
+
+#define QF_TRY(x)                          \
+  do {                                     \
+    qfdtd_status s_ = (x);                 \
+    if (s_ != QFDTD_OK) return s_;         \
+  } while (0)
+
+// run a family separately for each distinct k (kernels templated on k)
+qfdtd_status run_by_k(Fam f, std::vector<Entry> &es, bool dbl) {
+  for (int KS = 1; KS <= MAX_STATES; ++KS) {
+    std::vector<Entry> sub;
+    for (auto &e : es)
+      if (e.c->k == KS) sub.push_back(e);
+    QF_TRY(run_family(f, sub, dbl, KS));
+  }
+  return QFDTD_OK;
+}
+
+// ------------------------------------------------------------- measurement
+
+// parity projection + orthonormalisation; leaves every state in psi
+qfdtd_status orthonormalise(std::vector<qfdtd_ctx *> &ms) {
+  if (ms.empty()) return QFDTD_OK;
+  const bool dbl = ms[0]->dbl;
+  std::vector<Entry> par, gram, fin, app;
+  for (auto *c : ms) {
+    const long long tot = (long long)c->k * c->n3();
+    int src = c->cur;    // 0: psi, 1: alt
+    if (c->any_parity) {
+      par.push_back({c, 0, src ? (uint32_t)M_SWAP : 0u, ew_tiles_host(tot), 0});
+      src = 1 - src;
+    }
+    gram.push_back({c, 0, src ? (uint32_t)M_SWAP : 0u, c->nblk_red, 0});
+    fin.push_back({c, 0, 0u, 1, 0});
+    app.push_back({c, 0, src ? (uint32_t)M_SWAP : 0u, ew_tiles_host((long long)c->n3()), 0});
+    c->cur = 0;
+    c->fresh = false;
+  }
+  QF_TRY(run_family(F_PARITY, par, dbl));
+  QF_TRY(run_by_k(F_GRAM, gram, dbl));
+  QF_TRY(run_family(F_GFIN, fin, dbl));
+  QF_TRY(run_by_k(F_APPLY, app, dbl));
+  return QFDTD_OK;
+}
+
+// FP64 forward transform of the scratch copy (FFT members)
+qfdtd_status fwd64(std::vector<qfdtd_ctx *> &ms) {
+  std::vector<Entry> pl, rw, c2, c1;
+  for (auto *c : ms) {
+    if (c->plane64) pl.push_back({c, 1, M_FWD, plane_tiles(c->N, c->k), 0});
+    else {
+      rw.push_back({c, 1, M_FWD, row_tiles(c->N, c->k), 0});
+      c2.push_back({c, 1, M_FWD, col_tiles(c->N, c->k, true), 0});
+    }
+    c1.push_back({c, 1, M_FWD | M_AXIS1, col_tiles(c->N, c->k, true), 0});
+  }
+  QF_TRY(run_family(F_PLANE, pl, true));
+  QF_TRY(run_family(F_ROW, rw, true));
+  QF_TRY(run_family(F_COL, c2, true));
+  QF_TRY(run_family(F_COL, c1, true));
+  return QFDTD_OK;
+}
+
+// E_i = <psi_i|H|psi_i>/<psi_i|psi_i> in FP64; `slot` >= 0 also records a trace row
+qfdtd_status energies(std::vector<qfdtd_ctx *> &ms, bool with_trace) {
+  if (ms.empty()) return QFDTD_OK;
+  const bool dbl = ms[0]->dbl;
+  std::vector<Entry> ep, to, kp, fin;
+  std::vector<qfdtd_ctx *> ffts;
+  for (auto *c : ms) {
+    ep.push_back({c, 0, 0u, c->nblk_red, 0});
+    if (c->fft()) {
+      to.push_back({c, 0, 0u, ew_tiles_host((long long)c->k * c->n3()), 0});
+      kp.push_back({c, 1, 0u, c->nblk_red, 0});
+      ffts.push_back(c);
+    }
+    int slot = -1;
+    if (with_trace && c->trace_on && c->trace_n < c->trace_cap) slot = (int)c->trace_n++;
+    fin.push_back({c, 0, 0u, 1, slot});
+  }
+  QF_TRY(run_by_k(F_EPART, ep, dbl));
+  QF_TRY(run_family(F_TO64, to, dbl));
+  QF_TRY(fwd64(ffts));
+  QF_TRY(run_by_k(F_KPART, kp, true));
+  QF_TRY(run_family(F_EFIN, fin, dbl));
+  return QFDTD_OK;
+}
+
+// ------------------------------------------------------------- one chunk
+
+qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
+  if (ms.empty()) return QFDTD_OK;
+  const bool dbl = ms[0]->dbl;
+  int maxn = 0;
+  for (int v : n) maxn = v > maxn ? v : maxn;
+  std::vector<Entry> pl, rw, c2, c1, sten;
+  // chunk start: h then forward transforms along x3 (and x2)
+  for (size_t j = 0; j < ms.size(); ++j) {
+    qfdtd_ctx *c = ms[j];
+    if (!c->fft() || n[j] <= 0) continue;
+    if (c->plane) pl.push_back({c, 0, M_PRE | M_FWD, plane_tiles(c->N, c->k), 0});
+    else {
+      rw.push_back({c, 0, M_PRE | M_FWD, row_tiles(c->N, c->k), 0});
+      c2.push_back({c, 0, M_FWD, col_tiles(c->N, c->k, dbl), 0});
+    }
+  }
+  QF_TRY(run_family(F_PLANE, pl, dbl));
+  QF_TRY(run_family(F_ROW, rw, dbl));
+  QF_TRY(run_family(F_COL, c2, dbl));
+  for (int s = 0; s < maxn; ++s) {
+    c1.clear(); c2.clear(); pl.clear(); rw.clear(); sten.clear();
+    std::vector<Entry> c2f;
+    for (size_t j = 0; j < ms.size(); ++j) {
+      qfdtd_ctx *c = ms[j];
+      if (s >= n[j]) continue;
+      if (!c->fft()) {
+        sten.push_back({c, 0, c->cur ? (uint32_t)M_SWAP : 0u, ew_tiles_host((long long)c->k * c->n3()), 0});
+        c->cur ^= 1;
+        continue;
+      }
+      const bool last = (s == n[j] - 1);
+      const uint32_t rs = last ? (M_INV | M_POST) : (M_INV | M_MID | M_FWD);
+      c1.push_back({c, 0, M_FWD | M_KIN | M_INV | M_AXIS1, col_tiles(c->N, c->k, dbl), 0});
+      if (c->plane) pl.push_back({c, 0, rs, plane_tiles(c->N, c->k), 0});
+      else {
+        c2.push_back({c, 0, M_INV, col_tiles(c->N, c->k, dbl), 0});
+        rw.push_back({c, 0, rs, row_tiles(c->N, c->k), 0});
+        if (!last) c2f.push_back({c, 0, M_FWD, col_tiles(c->N, c->k, dbl), 0});
+      }
+    }
+    QF_TRY(run_family(F_COL, c1, dbl));
+    QF_TRY(run_family(F_COL, c2, dbl));
+    QF_TRY(run_family(F_PLANE, pl, dbl));
+    QF_TRY(run_family(F_ROW, rw, dbl));
+    QF_TRY(run_family(F_COL, c2f, dbl));
+    QF_TRY(run_family(F_STENCIL, sten, dbl));
+  }
+  return QFDTD_OK;
+}
+
+qfdtd_status upload_desc(qfdtd_ctx *c) {
+  QF_HIP(c, hipMemcpyAsync(c->d_desc, c->hd, sizeof(c->hd), hipMemcpyHostToDevice, c->st));
+  return QFDTD_OK;
+}
+
+qfdtd_status set_dt(qfdtd_ctx *c, double dt) {
+  if (dt == c->cur_dt) return QFDTD_OK;
+  launch_dt_tables(c->dbl, c->v64, c->vcomplex ? 1 : 0, c->N, dt, c->vtab, c->hfac, c->h2fac, c->ktab, c->ksym64,
+                   c->kin, c->st);
+  QF_LAUNCHED(c);
+  for (int w = 0; w < 2; ++w) {
+    c->hd[w].dt = dt;
+    c->hd[w].stencil_c = dt / (2.0 * c->m * c->a * c->a);
+  }
+  QF_TRY(upload_desc(c));
+  // the descriptor upload reads host memory that may change again: wait for it
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  c->cur_dt = dt;
+  return QFDTD_OK;
+}
+
+qfdtd_status check_status(qfdtd_ctx *c, bool wait) {
+  if (!c->status_pending) return c->poisoned ? QFDTD_E_NUMERIC : QFDTD_OK;
+  if (wait) QF_HIP(c, hipEventSynchronize(c->status_ev));
+  else if (hipEventQuery(c->status_ev) != hipSuccess) return QFDTD_OK;
+  c->status_pending = false;
+  if (*c->h_status != 0.0) {
+    c->poisoned = true;
+    c->set_mask = 0;
+    return fail(c, QFDTD_E_NUMERIC, "non-finite value or collapsed norm during orthonormalisation");
+  }
+  return QFDTD_OK;
+}
+
+qfdtd_status post_status(qfdtd_ctx *c) {
+  QF_HIP(c, hipMemcpyAsync(c->h_status, c->energy + 2 * MAX_STATES, sizeof(double), hipMemcpyDeviceToHost, c->st));
+  QF_HIP(c, hipEventRecord(c->status_ev, c->st));
+  c->status_pending = true;
+  return QFDTD_OK;
+}
+
+qfdtd_status validate_common(qfdtd_ctx *c) {
+  if (c->poisoned) return fail(c, QFDTD_E_STATE, "context poisoned by an earlier numeric failure; set every state again");
+  const uint32_t all = (c->k >= 32) ? 0xffffffffu : ((1u << c->k) - 1u);
+  if ((c->set_mask & all) != all) return fail(c, QFDTD_E_STATE, "not every state has been set");
+  return QFDTD_OK;
+}
+
+qfdtd_status batch_evolve_impl(qfdtd_ctx *const *members, int32_t n, const int64_t *steps, const double *dt) {
+  std::vector<qfdtd_ctx *> ms;
+  std::vector<int64_t> rem;
+  for (int j = 0; j < n; ++j) {
+    qfdtd_ctx *c = members[j];
+    QF_TRY(check_status(c, false));
+    QF_TRY(validate_common(c));
+    if (!(dt[j] > 0.0) || !std::isfinite(dt[j])) return fail(c, QFDTD_E_UNSTABLE_DT, "dt must be positive and finite");
+    if (c->kin == KIN_FDTD && dt[j] > c->m * c->a * c->a / 3.0)
+      return fail(c, QFDTD_E_UNSTABLE_DT, "H_K^(0) needs dt <= m a^2 / 3");
+    if (steps[j] < 0) return fail(c, QFDTD_E_INVALID, "steps must be >= 0");
+    if (j > 0 && (c->dbl != members[0]->dbl || c->st != members[0]->st))
+      return fail(c, QFDTD_E_INVALID, "batch members need the same precision and stream");
+    for (int i = 0; i < j; ++i)
+      if (members[i] == c) return fail(c, QFDTD_E_INVALID, "a context appears twice in the batch");
+  }
+  for (int j = 0; j < n; ++j) {
+    QF_TRY(set_dt(members[j], dt[j]));
+    ms.push_back(members[j]);
+    rem.push_back(steps[j]);
+  }
+  std::vector<qfdtd_ctx *> fr;
+  for (auto *c : ms)
+    if (c->fresh) fr.push_back(c);
+  QF_TRY(orthonormalise(fr));
+  for (;;) {
+    std::vector<qfdtd_ctx *> act;
+    std::vector<int> cn;
+    for (size_t j = 0; j < ms.size(); ++j)
+      if (rem[j] > 0) {
+        act.push_back(ms[j]);
+        cn.push_back((int)(rem[j] < ms[j]->K ? rem[j] : ms[j]->K));
+      }
+    if (act.empty()) break;
+    QF_TRY(run_chunk(act, cn));
+    QF_TRY(orthonormalise(act));
+    std::vector<qfdtd_ctx *> tr;
+    for (auto *c : act)
+      if (c->trace_on) tr.push_back(c);
+    QF_TRY(energies(tr, true));
+    size_t q = 0;
+    for (size_t j = 0; j < ms.size(); ++j)
+      if (rem[j] > 0) rem[j] -= cn[q++];
+  }
+  for (auto *c : ms) QF_TRY(post_status(c));
+  return QFDTD_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+size_t qfdtd_footprint(int32_t N, int32_t kinetic, int32_t precision, int32_t n_states) {
+  if (N <= 0 || n_states <= 0) return 0;
+  const size_t n3 = (size_t)N * N * N, k = (size_t)n_states;
+  const size_t cs = precision ? 16 : 8, rs = precision ? 8 : 4;
+  size_t b = k * n3 * cs;                                  // psi
+  b += k * n3 * cs;                                        // alt (upper bound)
+  b += n3 * 16;                                            // v64 (upper bound: complex)
+  b += (kinetic == KIN_FDTD ? 1 : 2) * n3 * 2 * rs;        // vtab or h, h^2 (upper bound: complex)
+  b += k * n3 * 16;                                        // FP64 scratch
+  b += 2 * 1024 * MAX_PAIRS * 2 * 8 + 64 * 1024;           // partials, small tables
+  return b;
+}
+
+qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_t kinetic, const qfdtd_potential *V,
+                          const qfdtd_options *opt) {
+  if (!out) return fail(nullptr, QFDTD_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!V) return fail(nullptr, QFDTD_E_INVALID, "potential is NULL");
+  if (kinetic < 0 || kinetic > 3) return fail(nullptr, QFDTD_E_INVALID, "kinetic must be 0..3");
+  if (!(a > 0.0) || !std::isfinite(a)) return fail(nullptr, QFDTD_E_INVALID, "a must be > 0");
+  if (!(m > 0.0) || !std::isfinite(m)) return fail(nullptr, QFDTD_E_INVALID, "m must be > 0");
+  if (N < 8 || (N & 1)) return fail(nullptr, QFDTD_E_UNSUPPORTED_N, "N must be even and >= 8");
+  if (kinetic != KIN_FDTD && (N > 256 || !smooth235(N)))
+    return fail(nullptr, QFDTD_E_UNSUPPORTED_N, "FFT kinetic terms need N <= 256 with factors 2, 3, 5 only");
+  if (kinetic == KIN_FDTD && N > 512) return fail(nullptr, QFDTD_E_UNSUPPORTED_N, "N must be <= 512");
+  qfdtd_options o;
+  std::memset(&o, 0, sizeof(o));
+  o.n_states = 3;
+  if (opt) o = *opt;
+  if (o.precision != 0 && o.precision != 1) return fail(nullptr, QFDTD_E_INVALID, "precision must be 0 or 1");
+  if (o.n_states < 1 || o.n_states > MAX_STATES) return fail(nullptr, QFDTD_E_INVALID, "n_states must be 1..8");
+  if (o.measure_every < 0) return fail(nullptr, QFDTD_E_INVALID, "measure_every must be >= 0");
+  if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr))
+    return fail(nullptr, QFDTD_E_INVALID, "dev_alloc and dev_free must be given together");
+  if (V->kind < 0 || V->kind > 4) return fail(nullptr, QFDTD_E_INVALID, "unknown potential kind");
+  if (V->kind == 0 && !V->grid) return fail(nullptr, QFDTD_E_INVALID, "QFDTD_V_GRID needs grid");
+  if (V->kind == 4) {
+    if (!V->knots || V->n_knots < 3 || V->n_knots > 4096) return fail(nullptr, QFDTD_E_INVALID, "spline needs 3..4096 knots");
+    for (int j = 1; j < V->n_knots; ++j)
+      if (!(V->knots[2 * j] > V->knots[2 * (j - 1)])) return fail(nullptr, QFDTD_E_INVALID, "spline knots must increase in r");
+  }
+  for (int i = 0; i < o.n_states && o.sectors; ++i)
+    if (o.sectors[i] < 0 || o.sectors[i] > 5) return fail(nullptr, QFDTD_E_INVALID, "sector must be 0..5");
+  static bool inited = false;
+  if (!inited) {
+    hipError_t e = fft_kernels_init();
+    if (e != hipSuccess) return fail(nullptr, QFDTD_E_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
+    inited = true;
+  }
+  qfdtd_ctx *c = new qfdtd_ctx();
+  c->N = N; c->a = a; c->m = m; c->kin = kinetic;
+  c->prec = o.precision; c->dbl = o.precision == 1;
+  c->k = o.n_states;
+  c->K = o.measure_every > 0 ? o.measure_every : 50;
+  c->st = (hipStream_t)o.hip_stream;
+  c->af = o.dev_alloc; c->ff = o.dev_free; c->au = o.alloc_user;
+  for (int i = 0; i < c->k; ++i) {
+    const int s = o.sectors ? o.sectors[i] : 0;
+    if (s < 0 || s > 5) { delete c; return fail(nullptr, QFDTD_E_INVALID, "sector must be 0..5"); }
+    c->sectors[i] = s;
+    if (s) c->any_parity = true;
+  }
+  const size_t n3 = c->n3();
+  // complex potential?
+  if (V->grid) {
+    for (size_t g = 0; g < n3; ++g)
+      if (V->grid[2 * g + 1] != 0.0) { c->vcomplex = true; break; }
+  }
+  c->plane = c->fft() && plane_lds(N, c->dbl) <= 160 * 1024 && (size_t)N * N <= 16 * PLANE_THREADS;
+  c->plane64 = c->fft() && plane_lds(N, true) <= 160 * 1024 && (size_t)N * N <= 16 * PLANE_THREADS;
+  c->nblk_red = (int)((n3 + 2047) / 2048);
+  if (c->nblk_red > 1024) c->nblk_red = 1024;
+  if (c->nblk_red < 1) c->nblk_red = 1;
+  c->trace_on = o.trace_energies ? 1 : 0;
+  c->trace_cap = c->trace_on ? 4096 : 0;
+
+  auto bail = [&](qfdtd_status s, const std::string &msg) {
+    free_all(c);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    if (c->status_ev) (void)hipEventDestroy(c->status_ev);
+    delete c;
+    return fail(nullptr, s, msg);
+  };
+  const size_t cs = c->csz(), rs = c->rsz();
+  const size_t fsz = (c->vcomplex ? 2 : 1) * rs;
+  c->psi = dalloc(c, c->k * n3 * cs);
+  if (!c->fft() || c->any_parity) c->alt = dalloc(c, c->k * n3 * cs);
+  c->v64 = (double *)dalloc(c, n3 * 8 * (c->vcomplex ? 2 : 1));
+  if (!c->fft()) c->vtab = dalloc(c, n3 * fsz);
+  else { c->hfac = dalloc(c, n3 * fsz); c->h2fac = dalloc(c, n3 * fsz); }
+  c->ktab = dalloc(c, N * rs);
+  c->tw = dalloc(c, N * cs);
+  c->tw64 = (double2 *)dalloc(c, N * 16);
+  c->ksym64 = (double *)dalloc(c, N * 8);
+  c->scratch64 = (double2 *)dalloc(c, c->k * n3 * 16);
+  c->partials = (double *)dalloc(c, 2 * (size_t)c->nblk_red * MAX_PAIRS * 2 * 8);
+  c->coef = (double *)dalloc(c, MAX_STATES * MAX_STATES * 2 * 8);
+  c->energy = (double *)dalloc(c, (2 * MAX_STATES + 8) * 8);
+  if (c->trace_on) c->trace = (double *)dalloc(c, (size_t)c->trace_cap * c->k * 2 * 8);
+  c->d_desc = (PassDesc *)dalloc(c, sizeof(c->hd));
+  bool ok = c->psi && c->v64 && c->ktab && c->tw && c->tw64 && c->ksym64 && c->scratch64 && c->partials && c->coef &&
+            c->energy && c->d_desc && (c->fft() || (c->alt && c->vtab)) && (!c->fft() || (c->hfac && c->h2fac)) &&
+            (!c->any_parity || c->alt) && (!c->trace_on || c->trace);
+  if (!ok) return bail(QFDTD_E_NOMEM, "device allocation failed");
+  if (hipHostMalloc((void **)&c->h_status, sizeof(double)) != hipSuccess) return bail(QFDTD_E_NOMEM, "pinned allocation failed");
+  *c->h_status = 0.0;
+  if (hipEventCreateWithFlags(&c->status_ev, hipEventDisableTiming) != hipSuccess)
+    return bail(QFDTD_E_DEVICE, "event creation failed");
+
+  // ---- potential (FP64, on the device)
+  double *d_knots = nullptr;
+  int nk = 0;
+  if (V->kind == 4) {
+    nk = V->n_knots;
+    std::vector<double> h(3 * nk);
+    std::vector<double> x(nk), y(nk), M(nk, 0.0);
+    for (int j = 0; j < nk; ++j) { x[j] = V->knots[2 * j]; y[j] = V->knots[2 * j + 1]; }
+    // natural spline: second derivatives from the tridiagonal system (Thomas algorithm)
+    std::vector<double> cp(nk, 0.0), dp(nk, 0.0);
+    for (int j = 1; j < nk - 1; ++j) {
+      const double h0 = x[j] - x[j - 1], h1 = x[j + 1] - x[j];
+      const double sub = h0, diag = 2.0 * (h0 + h1), sup = h1;
+      const double rhs = 6.0 * ((y[j + 1] - y[j]) / h1 - (y[j] - y[j - 1]) / h0);
+      const double den = diag - sub * cp[j - 1];
+      cp[j] = sup / den;
+      dp[j] = (rhs - sub * dp[j - 1]) / den;
+    }
+    for (int j = nk - 2; j >= 1; --j) M[j] = dp[j] - cp[j] * M[j + 1];
+    for (int j = 0; j < nk; ++j) { h[j] = x[j]; h[nk + j] = y[j]; h[2 * nk + j] = M[j]; }
+    if (hipMalloc(&d_knots, h.size() * 8) != hipSuccess) return bail(QFDTD_E_NOMEM, "knot buffer");
+    if (hipMemcpy(d_knots, h.data(), h.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d_knots);
+      return bail(QFDTD_E_DEVICE, "knot upload");
+    }
+  }
+  const double2 *d_add = nullptr;
+  if (V->grid) {
+    if (hipMemcpyAsync(c->scratch64, V->grid, n3 * 16, hipMemcpyHostToDevice, c->st) != hipSuccess) {
+      if (d_knots) (void)hipFree(d_knots);
+      return bail(QFDTD_E_DEVICE, "potential grid upload");
+    }
+    d_add = c->scratch64;
+  }
+  launch_potential(c->v64, c->vcomplex ? 1 : 0, N, a, V->kind, V->p, d_knots, nk, d_add, c->st);
+  launch_tables(c->dbl, c->tw, c->tw64, c->ksym64, N, kinetic, a, m, c->st);
+  hipError_t le = hipGetLastError();
+  hipError_t se = hipStreamSynchronize(c->st);
+  if (d_knots) (void)hipFree(d_knots);
+  if (le != hipSuccess || se != hipSuccess)
+    return bail(QFDTD_E_DEVICE, std::string("setup kernels: ") + hipGetErrorString(le != hipSuccess ? le : se));
+
+  // ---- descriptors
+  for (int w = 0; w < 2; ++w) {
+    PassDesc &d = c->hd[w];
+    std::memset(&d, 0, sizeof(d));
+    d.psi = w ? (void *)c->scratch64 : c->psi;
+    d.alt = c->alt;
+    d.vtab = c->vtab;
+    d.hfac = c->hfac;
+    d.h2fac = c->h2fac;
+    d.ktab = c->ktab;
+    d.tw = w ? (const void *)c->tw64 : c->tw;
+    d.tw64 = c->tw64;
+    d.ksym64 = c->ksym64;
+    d.v64 = c->v64;
+    d.scratch64 = c->scratch64;
+    d.partials = c->partials;
+    d.coef = c->coef;
+    d.energy = c->energy;
+    d.trace = c->trace;
+    d.N = N; d.k = c->k; d.kin = kinetic; d.vcomplex = c->vcomplex ? 1 : 0;
+    d.nst = make_plan(N, d.radix);
+    for (int i = 0; i < c->k; ++i) d.sector[i] = c->sectors[i];
+    d.nblk_red = c->nblk_red;
+    d.a = a; d.m = m; d.dt = 0.0; d.stencil_c = 0.0;
+    d.inv_n3 = 1.0 / (double)n3;
+  }
+  if (upload_desc(c) != QFDTD_OK || hipMemsetAsync(c->energy, 0, (2 * MAX_STATES + 8) * 8, c->st) != hipSuccess ||
+      hipStreamSynchronize(c->st) != hipSuccess)
+    return bail(QFDTD_E_DEVICE, "descriptor upload");
+  *out = c;
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_set_state(qfdtd_ctx *c, int32_t i, const double *psi) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  if (!psi) return fail(c, QFDTD_E_INVALID, "psi is NULL");
+  if (i < 0 || i >= c->k) return fail(c, QFDTD_E_INVALID, "state index out of range");
+  QF_TRY(check_status(c, true));
+  const size_t n3 = c->n3();
+  QF_HIP(c, hipMemcpyAsync(c->scratch64, psi, n3 * 16, hipMemcpyHostToDevice, c->st));
+  launch_from64_slot(c->dbl, (char *)c->psi + (size_t)i * n3 * c->csz(), c->scratch64, n3, c->st);
+  QF_LAUNCHED(c);
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  c->set_mask |= 1u << i;
+  c->fresh = true;
+  const uint32_t all = (1u << c->k) - 1u;
+  if ((c->set_mask & all) == all && c->poisoned) {
+    c->poisoned = false;
+    QF_HIP(c, hipMemsetAsync(c->energy + 2 * MAX_STATES, 0, 8, c->st));
+  }
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_set_state_device(qfdtd_ctx *c, int32_t i, const void *psi_dev) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  if (!psi_dev) return fail(c, QFDTD_E_INVALID, "psi_dev is NULL");
+  if (i < 0 || i >= c->k) return fail(c, QFDTD_E_INVALID, "state index out of range");
+  QF_TRY(check_status(c, false));
+  const size_t bytes = c->n3() * c->csz();
+  QF_HIP(c, hipMemcpyAsync((char *)c->psi + (size_t)i * bytes, psi_dev, bytes, hipMemcpyDeviceToDevice, c->st));
+  c->set_mask |= 1u << i;
+  c->fresh = true;
+  const uint32_t all = (1u << c->k) - 1u;
+  if ((c->set_mask & all) == all && c->poisoned) {
+    c->poisoned = false;
+    QF_HIP(c, hipMemsetAsync(c->energy + 2 * MAX_STATES, 0, 8, c->st));
+  }
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_evolve(qfdtd_ctx *c, int64_t steps, double dt) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  qfdtd_ctx *m[1] = {c};
+  return batch_evolve_impl(m, 1, &steps, &dt);
+}
+
+qfdtd_status qfdtd_batch_evolve(qfdtd_ctx *const *members, int32_t n, const int64_t *steps, const double *dt) {
+  if (!members || !steps || !dt || n < 1) return fail(nullptr, QFDTD_E_INVALID, "bad batch arguments");
+  for (int j = 0; j < n; ++j)
+    if (!members[j]) return fail(nullptr, QFDTD_E_INVALID, "NULL batch member");
+  return batch_evolve_impl(members, n, steps, dt);
+}
+
+static qfdtd_status measure_host(qfdtd_ctx *c) {
+  QF_TRY(check_status(c, true));
+  QF_TRY(validate_common(c));
+  std::vector<qfdtd_ctx *> one{c};
+  if (c->fresh) QF_TRY(orthonormalise(one));
+  QF_TRY(energies(one, false));
+  QF_TRY(post_status(c));
+  QF_TRY(check_status(c, true));
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_states(qfdtd_ctx *c, int32_t k, double *en, double *psi) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  if (k < 1 || k > c->k) return fail(c, QFDTD_E_INVALID, "k out of range");
+  QF_TRY(measure_host(c));
+  std::vector<double> e(2 * MAX_STATES);
+  QF_HIP(c, hipMemcpyAsync(e.data(), c->energy, 2 * MAX_STATES * 8, hipMemcpyDeviceToHost, c->st));
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  if (en) std::memcpy(en, e.data(), (size_t)2 * k * 8);
+  if (psi) {
+    const size_t n3 = c->n3();
+    for (int i = 0; i < k; ++i) {
+      const void *src = (const char *)c->psi + (size_t)i * n3 * c->csz();
+      if (c->dbl) {
+        QF_HIP(c, hipMemcpyAsync(psi + (size_t)i * 2 * n3, src, n3 * 16, hipMemcpyDeviceToHost, c->st));
+      } else {
+        launch_to64_slot(false, c->scratch64, src, n3, c->st);
+        QF_LAUNCHED(c);
+        QF_HIP(c, hipMemcpyAsync(psi + (size_t)i * 2 * n3, c->scratch64, n3 * 16, hipMemcpyDeviceToHost, c->st));
+      }
+    }
+    QF_HIP(c, hipStreamSynchronize(c->st));
+  }
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_states_device(qfdtd_ctx *c, int32_t k, double *en, void *psi_dev) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  if (k < 1 || k > c->k) return fail(c, QFDTD_E_INVALID, "k out of range");
+  QF_TRY(measure_host(c));
+  if (en) {
+    std::vector<double> e(2 * MAX_STATES);
+    QF_HIP(c, hipMemcpyAsync(e.data(), c->energy, 2 * MAX_STATES * 8, hipMemcpyDeviceToHost, c->st));
+    QF_HIP(c, hipStreamSynchronize(c->st));
+    std::memcpy(en, e.data(), (size_t)2 * k * 8);
+  }
+  if (psi_dev) QF_HIP(c, hipMemcpyAsync(psi_dev, c->psi, (size_t)k * c->n3() * c->csz(), hipMemcpyDeviceToDevice, c->st));
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_batch_energies(qfdtd_ctx *const *members, int32_t n, double *en) {
+  if (!members || n < 1 || !en) return fail(nullptr, QFDTD_E_INVALID, "bad batch arguments");
+  std::vector<qfdtd_ctx *> ms, fr;
+  int kmax = 0;
+  for (int j = 0; j < n; ++j) {
+    qfdtd_ctx *c = members[j];
+    if (!c) return fail(nullptr, QFDTD_E_INVALID, "NULL batch member");
+    QF_TRY(check_status(c, false));
+    QF_TRY(validate_common(c));
+    if (c->dbl != members[0]->dbl || c->st != members[0]->st)
+      return fail(c, QFDTD_E_INVALID, "batch members need the same precision and stream");
+    ms.push_back(c);
+    if (c->fresh) fr.push_back(c);
+    kmax = c->k > kmax ? c->k : kmax;
+  }
+  QF_TRY(orthonormalise(fr));
+  QF_TRY(energies(ms, false));
+  std::vector<double> e(2 * MAX_STATES + 8);
+  for (int j = 0; j < n; ++j) {
+    qfdtd_ctx *c = ms[j];
+    QF_HIP(c, hipMemcpyAsync(e.data(), c->energy, (2 * MAX_STATES + 1) * 8, hipMemcpyDeviceToHost, c->st));
+    QF_HIP(c, hipStreamSynchronize(c->st));
+    if (e[2 * MAX_STATES] != 0.0) {
+      c->poisoned = true;
+      c->set_mask = 0;
+      return fail(c, QFDTD_E_NUMERIC, "non-finite energy or collapsed norm");
+    }
+    for (int i = 0; i < kmax; ++i) {
+      en[2 * ((size_t)j * kmax + i)] = i < c->k ? e[2 * i] : 0.0;
+      en[2 * ((size_t)j * kmax + i) + 1] = i < c->k ? e[2 * i + 1] : 0.0;
+    }
+  }
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_energy_trace(qfdtd_ctx *c, double *out, int64_t cap, int64_t *n) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  if (!n) return fail(c, QFDTD_E_INVALID, "n is NULL");
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  *n = c->trace_n;
+  const int64_t rows = cap < c->trace_n ? cap : c->trace_n;
+  if (out && rows > 0 && c->trace)
+    QF_HIP(c, hipMemcpy(out, c->trace, (size_t)rows * c->k * 2 * 8, hipMemcpyDeviceToHost));
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_enable_kernel_timing(qfdtd_ctx *c, int32_t every) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  if (every < 0) return fail(c, QFDTD_E_INVALID, "every must be >= 0");
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  tcollect(c);
+  Timer &t = c->timer;
+  t.every = every;
+  for (int i = 0; i < TC_N; ++i) { t.seen[i] = 0; t.count[i] = 0; t.sum_ms[i] = 0; t.sum_bytes[i] = 0; }
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_kernel_stats(qfdtd_ctx *c, int32_t cls, int64_t *count, double *mean_ms, double *bytes) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  if (cls < 0 || cls >= TC_N) return fail(c, QFDTD_E_INVALID, "class out of range");
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  tcollect(c);
+  const Timer &t = c->timer;
+  if (count) *count = t.count[cls];
+  if (mean_ms) *mean_ms = t.count[cls] ? t.sum_ms[cls] / (double)t.count[cls] : 0.0;
+  if (bytes) *bytes = t.count[cls] ? t.sum_bytes[cls] / (double)t.count[cls] : 0.0;
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_transform_state(qfdtd_ctx *c, int32_t i, int32_t sign) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  if (!c->fft()) return fail(c, QFDTD_E_INVALID, "transform needs an FFT kinetic term");
+  if (i < 0 || i >= c->k || (sign != 1 && sign != -1)) return fail(c, QFDTD_E_INVALID, "bad state index or sign");
+  // a one-state view of slot i: temporarily point the main descriptor at it
+  PassDesc save = c->hd[0];
+  c->hd[0].psi = (char *)c->psi + (size_t)i * c->n3() * c->csz();
+  c->hd[0].k = 1;
+  QF_TRY(upload_desc(c));
+  std::vector<Entry> pl, rw, c2, c1;
+  const uint32_t dir = sign < 0 ? M_FWD : M_INV;
+  const bool dbl = c->dbl;
+  if (c->plane) pl.push_back({c, 0, dir, plane_tiles(c->N, 1), 0});
+  else {
+    rw.push_back({c, 0, dir, row_tiles(c->N, 1), 0});
+    c2.push_back({c, 0, dir, col_tiles(c->N, 1, dbl), 0});
+  }
+  c1.push_back({c, 0, dir | M_AXIS1 | (sign > 0 ? (uint32_t)M_SCALE : 0u), col_tiles(c->N, 1, dbl), 0});
+  qfdtd_status s = QFDTD_OK;
+  if (s == QFDTD_OK) s = run_family(F_PLANE, pl, dbl);
+  if (s == QFDTD_OK) s = run_family(F_ROW, rw, dbl);
+  if (s == QFDTD_OK) s = run_family(F_COL, c2, dbl);
+  if (s == QFDTD_OK) s = run_family(F_COL, c1, dbl);
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  c->hd[0] = save;
+  QF_TRY(upload_desc(c));
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  return s;
+}
+
+qfdtd_status qfdtd_state_pointer(qfdtd_ctx *c, int32_t i, void **ptr) {
+  if (!c || !ptr) return fail(c, QFDTD_E_INVALID, "NULL argument");
+  if (i < 0 || i >= c->k) return fail(c, QFDTD_E_INVALID, "state index out of range");
+  *ptr = (char *)c->psi + (size_t)i * c->n3() * c->csz();
+  return QFDTD_OK;
+}
+
+void qfdtd_destroy(qfdtd_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  for (auto &r : c->timer.pool) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  free_all(c);
+  if (c->h_status) (void)hipHostFree(c->h_status);
+  if (c->status_ev) (void)hipEventDestroy(c->status_ev);
+  delete c;
+}
+
+const char *qfdtd_last_error(const qfdtd_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared entry
+point, and rejects invalid arguments before touching the device."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qfdtd.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set(re.findall(r"\b(qfdtd_[a-z_]+)\s*\(", txt))
+    return sorted(n for n in names if not n.endswith("_fn"))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2211_10185_amd import _lib
+    return _lib
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = header_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L.lib, n), n
+    assert set(names) == set(L.exported_symbols())
+
+
+def _create(L, N=32, a=0.25, m=1.0, kin=1, vkind=1, prec=0, k=3, sectors=None, K=0, knots=None):
+    pot = L.Potential()
+    pot.kind = vkind
+    pot.p[0] = 1.0
+    keep = []
+    if knots is not None:
+        kn = np.ascontiguousarray(knots, dtype=np.float64)
+        keep.append(kn)
+        pot.knots = kn.ctypes.data_as(ct.POINTER(ct.c_double))
+        pot.n_knots = kn.shape[0]
+    opt = L.Options()
+    opt.precision = prec
+    opt.n_states = k
+    opt.measure_every = K
+    if sectors is not None:
+        sec = (ct.c_int32 * k)(*sectors)
+        keep.append(sec)
+        opt.sectors = ct.cast(sec, ct.POINTER(ct.c_int32))
+    ctx = ct.c_void_p()
+    st = L.lib.qfdtd_create(ct.byref(ctx), N, a, m, kin, ct.byref(pot), ct.byref(opt))
+    return st, ctx
+
+
+@pytest.mark.parametrize("N,kin,code", [(31, 1, -2), (6, 1, -2), (14, 1, -2), (7 * 8, 2, -2), (288, 1, -2),
+                                        (514, 0, -2), (44, 3, -2)])
+def test_unsupported_lattice_sizes(L, N, kin, code):
+    st, ctx = _create(L, N=N, kin=kin)
+    assert st == code
+    assert not ctx.value
+    assert L.lib.qfdtd_last_error(None)
+
+
+@pytest.mark.parametrize("kw", [dict(a=0.0), dict(m=-1.0), dict(kin=4), dict(vkind=9), dict(prec=2),
+                                dict(k=0), dict(k=9), dict(sectors=[0, 7, 0]), dict(K=-1),
+                                dict(vkind=0), dict(vkind=4, knots=np.array([[0, 1], [1, 2.0]])),
+                                dict(vkind=4, knots=np.array([[0, 1], [2, 2.0], [1, 3.0]]))])
+def test_invalid_arguments(L, kw):
+    st, ctx = _create(L, **kw)
+    assert st == -1
+    assert not ctx.value
+
+
+def test_null_context_calls(L):
+    assert L.lib.qfdtd_evolve(None, 10, 0.01) == -1
+    assert L.lib.qfdtd_set_state(None, 0, None) == -1
+    assert L.lib.qfdtd_states(None, 1, None, None) == -1
+    L.lib.qfdtd_destroy(None)
+
+
+def test_footprint_scales_with_volume(L):
+    f1 = L.lib.qfdtd_footprint(64, 1, 0, 3)
+    f2 = L.lib.qfdtd_footprint(128, 1, 0, 3)
+    assert 7.5 < f2 / f1 < 8.5
+    assert L.lib.qfdtd_footprint(128, 1, 1, 3) > f2
+    assert L.lib.qfdtd_footprint(0, 1, 0, 3) == 0
