@@ -1,0 +1,206 @@
+"""Benchmark: lattice site-updates/s of the imaginary-time evolution on one MI355X.
+
+Workload (one bench step): the harmonic-oscillator problem on a 128^3 lattice
+(a = 0.25, m = 1, V = r^2/2 centred on the lattice, 3 states from seeded
+Gaussian noise, dt = a^2/8, 5000 steps, orthonormalisation every 50 steps,
+complex64 states with FP64 reductions), solved twice: with the 7-point FDTD
+kinetic term H_K^(0) and with the 4 sin^2(k/2) FFT kinetic term H_K^(2), each
+to its three lowest energies.  The seeded initial states are resident in HBM
+before the timed region; each step copies them in on the device, evolves, and
+reads back the energies.
+
+Prints one JSON line.  value = site-updates/s = 2 solves x 3 states x 128^3
+sites x 5000 steps / (seconds per bench step).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+CLASS_NAMES = {0: "plane_pass", 1: "row_pass", 2: "column_pass", 3: "fdtd_stencil"}
+KERNEL_SYMBOLS = {0: "k_plane", 1: "k_row", 2: "k_col", 3: "k_stencil"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--imag-steps", type=int, default=5000, help="imaginary-time steps per solve")
+    ap.add_argument("--timing-every", type=int, default=8, help="time one launch in this many")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2211_10185_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(cls_name):
+    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernels."""
+    path = os.path.join(ROOT, "profiles", "traffic_ho128.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    k = rec.get("kernels", {}).get(cls_name)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(p_fdtd, p_fft, seconds):
+    """The oracle, untuned, on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle as O
+    t_budget = seconds / 2
+    res = {}
+    total_su, total_t = 0.0, 0.0
+    for p in (p_fdtd, p_fft):
+        V = O.problem_potential(p)
+        init = p.init_states()
+        sectors = [0] * p.k
+        periodic = p.kinetic != O.K_FDTD
+        st = O.prepare(init, sectors, periodic)
+        T = O.kinetic_symbol(p.kinetic, p.N, p.a, p.m) if periodic else None
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < t_budget:
+            if periodic:
+                st = [O.step_split(s, T, V, p.dt) for s in st]
+            else:
+                st = [O.step_fdtd(s, V, p.dt, p.a, p.m) for s in st]
+            n += 1
+        dt_ = time.perf_counter() - t0
+        total_su += n * p.k * p.N ** 3
+        total_t += dt_
+        res[p.label] = n
+    return {"value": total_su / total_t, "unit": "site-updates/s", "cores": O.WORKERS, "kind": "oracle",
+            "sample": "FP64 numpy/scipy oracle steps of the same 128^3 x 3-state problems "
+                      "(%d FDTD steps, %d FFT steps, %.0f s wall); orthonormalisation excluded"
+                      % (res[p_fdtd.label], res[p_fft.label], total_t)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(one lattice per GPU; sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synthetic as S
+    from paper_2211_10185_amd.solver import Solver
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    p_fdtd = S.config2(S.K_FDTD)
+    p_fft = S.config2(S.K_NR_SIN2)
+    for p in (p_fdtd, p_fft):
+        p.steps = args.imag_steps
+    N, k = p_fft.N, p_fft.k
+    init = p_fft.init_states()        # same seed for both forms
+    init_dev = torch.from_numpy(init.astype(np.complex64)).to(dev)
+    solvers = [Solver.from_problem(p) for p in (p_fdtd, p_fft)]
+    torch.cuda.synchronize()
+
+    lat = []
+
+    def one_step():
+        out = []
+        for s, p in zip(solvers, (p_fdtd, p_fft)):
+            t0 = time.perf_counter()
+            for i in range(k):
+                s._c(s_lib.qfdtd_set_state_device(s.ctx, i, init_dev[i].data_ptr()))
+            s.evolve(p.steps, p.dt)
+            E = s.energies()
+            lat.append(time.perf_counter() - t0)
+            out.append(E)
+        return out
+
+    from paper_2211_10185_amd import _lib
+    s_lib = _lib.lib
+
+    for _ in range(args.warmup):
+        one_step()
+    lat.clear()
+    for s in solvers:
+        s.enable_kernel_timing(args.timing_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        energies = one_step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    su_per_step = 2 * k * N ** 3 * args.imag_steps
+    value = su_per_step / (elapsed / args.steps)
+
+    # dominant kernel class by total time in the timed region
+    stats = {}
+    for cls in (0, 1, 2, 3):
+        cnt, tot_ms, tot_b = 0, 0.0, 0.0
+        for s in solvers:
+            n, mean_ms, b = s.kernel_stats(cls)
+            cnt += n
+            tot_ms += n * mean_ms
+            tot_b += n * b
+        if cnt:
+            stats[cls] = (cnt, tot_ms / cnt, tot_b / cnt, tot_ms)
+    dom = max(stats, key=lambda c: stats[c][3])
+    cnt, mean_ms, bytes_per_launch, _ = stats[dom]
+    achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(CLASS_NAMES[dom])
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "kernel": KERNEL_SYMBOLS[dom], "mean_launch_ms": round(mean_ms, 5),
+            "algorithmic_bytes_per_launch": bytes_per_launch, "timed_launches": cnt,
+            "by_class": {CLASS_NAMES[c]: {"mean_ms": round(v[1], 5), "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1),
+                                          "share": round(v[3] / sum(x[3] for x in stats.values()), 3)}
+                         for c, v in stats.items()}}
+    lat_ms = sorted(1e3 * x for x in lat)
+    out = {
+        "metric": "lattice site-updates/s", "value": value, "unit": "site-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "harmonic oscillator 128^3, a=0.25, m=1, 3 states, dt=a^2/8, %d steps, "
+                               "FDTD H_K^(0) + FFT H_K^(2), complex64 states, FP64 reductions" % args.imag_steps,
+                   "N": N, "states": k, "imag_steps": args.imag_steps, "solves_per_step": 2,
+                   "reductions": "f64"},
+        "solves_per_s": 2 * args.steps / elapsed,
+        "solve_latency_ms": {"p50": lat_ms[len(lat_ms) // 2], "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))]},
+        "energies": {"fdtd": [round(e.real, 9) for e in energies[0]], "sin2": [round(e.real, 9) for e in energies[1]]},
+        "roofline": roof,
+    }
+    for s in solvers:
+        s.close()
+    if not args.no_cpu_baseline:
+        pf = S.config2(S.K_FDTD)
+        pk = S.config2(S.K_NR_SIN2)
+        out["cpu_baseline"] = cpu_baseline(pf, pk, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

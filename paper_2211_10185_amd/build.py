@@ -16,7 +16,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libqfdtd.so")
-SOURCES = ["fft_kernels.hip", "aux_kernels.hip", "qfdtd_api.hip"]
+# (source, object name, extra flags): the transform passes are instantiated
+# per lattice size in five groups so that they compile in parallel
+SOURCES = [("fft_inst.hip", "fft_inst%d" % g, ["-DQF_GROUP=%d" % g]) for g in range(5)] + [
+    ("aux_kernels.hip", "aux_kernels", []), ("qfdtd_api.hip", "qfdtd_api", [])]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code (see the
@@ -37,9 +40,9 @@ def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     jobs = []
-    for src in SOURCES:
-        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-        jobs.append((obj, [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]))
+    for src, name, extra in SOURCES:
+        obj = os.path.join(bdir, name + ".o")
+        jobs.append((obj, [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]))
     with cf.ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
         for out in ex.map(lambda j: _run(j[1]), jobs):
             if verbose and out.strip():

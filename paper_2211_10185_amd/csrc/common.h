@@ -109,8 +109,17 @@ __device__ __forceinline__ int find_entry(const LaunchList &L, int blk) {
   return lo;
 }
 
+// Transform-pass kernels instantiated for one lattice size (index 0: complex64,
+// 1: complex128); plane entries are null where an N^2 plane does not fit LDS.
+struct FftKernels {
+  const void *plane[2];
+  const void *row[2];
+  const void *col[2];
+  size_t plane_lds[2], row_lds[2], col_lds[2];
+  int plane_nt;
+};
+
 // Threads per block of each kernel family.
-constexpr int PLANE_THREADS = 1024;
 constexpr int LINE_THREADS = 256;
 constexpr int RED_THREADS = 256;
 

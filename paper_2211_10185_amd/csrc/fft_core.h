@@ -1,0 +1,254 @@
+// Compile-time FFT machinery for the transform passes (gfx950).
+//
+// Every supported lattice size N (even, 8..256, factors 2, 3, 5) gets its own
+// instantiation: the radix plan, the thread map of every stage and the LDS
+// index arithmetic are compile-time constants, so stages fully unroll, index
+// division becomes multiply-shift, and LDS addresses stay in the LDS address
+// space (ds_read/ds_write rather than flat accesses).
+//
+// 1D transforms are Stockham autosort FFTs: stage s with radix R and
+// Ns = product of the earlier radices reads x[j + r N/R], multiplies by the
+// twiddle w^{r (j mod Ns) N/(Ns R)} (w = e^{-2 pi i/N}, conjugated for the
+// inverse), applies a radix-R DFT and writes y[(j - j mod Ns) R + j mod Ns + r Ns].
+// Each stage reads its inputs into registers, synchronises and writes, so a
+// single LDS buffer holds the lines.
+#pragma once
+
+#include "common.h"
+
+namespace qf {
+
+// ------------------------------------------------------------- radix plans
+
+struct RPlan {
+  int n;
+  int r[8];
+};
+
+constexpr RPlan make_rplan(int N) {
+  RPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+  int m = N, a = 0, b = 0, c = 0;
+  while (m % 2 == 0) { m /= 2; ++a; }
+  while (m % 3 == 0) { m /= 3; ++b; }
+  while (m % 5 == 0) { m /= 5; ++c; }
+  // powers of two grouped into as few radix-16/8/4/2 stages as possible
+  const int twos[9][2] = {{0, 0}, {2, 0}, {4, 0}, {8, 0}, {16, 0}, {8, 4}, {8, 8}, {16, 8}, {16, 16}};
+  for (int i = 0; i < 2; ++i)
+    if (a <= 8 && twos[a][i]) p.r[p.n++] = twos[a][i];
+  for (int i = 0; i < b; ++i) p.r[p.n++] = 3;
+  for (int i = 0; i < c; ++i) p.r[p.n++] = 5;
+  return p;
+}
+
+constexpr bool fft_size_ok(int N) {
+  int m = N;
+  while (m % 2 == 0) m /= 2;
+  while (m % 3 == 0) m /= 3;
+  while (m % 5 == 0) m /= 5;
+  return m == 1 && N % 2 == 0 && N >= 8 && N <= 256;
+}
+
+// ------------------------------------------------------------- butterflies
+
+template <int R, bool INV, typename V> struct Dft;
+
+template <bool INV, typename V> struct Dft<2, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    V a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV, typename V> struct Dft<4, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    V t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    V t2 = cadd(v[1], v[3]), t3 = mul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+// x * e^{-+ 2 pi i m / 16} for a compile-time m (forward sign -, inverse +)
+template <int M, bool INV, typename V>
+__device__ __forceinline__ V rot16(V a) {
+  using T = decltype(a.x);
+  constexpr int m = M & 15;
+  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, r2 = 0.70710678118654752440;
+  constexpr double cs[16] = {1, c1, r2, s1, 0, -s1, -r2, -c1, -1, -c1, -r2, -s1, 0, s1, r2, c1};
+  constexpr double sn[16] = {0, s1, r2, c1, 1, c1, r2, s1, 0, -s1, -r2, -c1, -1, -c1, -r2, -s1};
+  if constexpr (m == 0) return a;
+  else if constexpr (m == 4) return mul_mi<INV>(a);
+  else if constexpr (m == 8) { V r; r.x = -a.x; r.y = -a.y; return r; }
+  else if constexpr (m == 12) return mul_mi<!INV>(a);
+  else {
+    const T c = (T)cs[m];
+    const T s = INV ? (T)sn[m] : (T)-sn[m];
+    V r;
+    r.x = a.x * c - a.y * s;
+    r.y = a.x * s + a.y * c;
+    return r;
+  }
+}
+
+template <bool INV, typename V> struct Dft<8, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    V e[4] = {v[0], v[2], v[4], v[6]};
+    V o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4, INV, V>::run(e);
+    Dft<4, INV, V>::run(o);
+    const V o1 = rot16<2, INV>(o[1]), o2 = rot16<4, INV>(o[2]), o3 = rot16<6, INV>(o[3]);
+    v[0] = cadd(e[0], o[0]); v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);   v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);   v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);   v[7] = csub(e[3], o3);
+  }
+};
+
+// 16 = 4 x 4: DFT4 over n1 of x[4 n1 + n2], twiddle w16^{n2 k1}, DFT4 over n2 -> X[k1 + 4 k2]
+template <bool INV, typename V> struct Dft<16, INV, V> {
+  template <int N2>
+  static __device__ __forceinline__ void col(V *v, V (&y)[4][4]) {
+    V t[4] = {v[N2], v[4 + N2], v[8 + N2], v[12 + N2]};
+    Dft<4, INV, V>::run(t);
+    y[0][N2] = t[0];
+    y[1][N2] = rot16<N2, INV>(t[1]);
+    y[2][N2] = rot16<2 * N2, INV>(t[2]);
+    y[3][N2] = rot16<3 * N2, INV>(t[3]);
+  }
+  static __device__ __forceinline__ void run(V *v) {
+    V y[4][4];
+    col<0>(v, y);
+    col<1>(v, y);
+    col<2>(v, y);
+    col<3>(v, y);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      Dft<4, INV, V>::run(y[k1]);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = y[k1][k2];
+    }
+  }
+};
+
+template <bool INV, typename V> struct Dft<3, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    using T = decltype(v[0].x);
+    const T s = (T)0.86602540378443864676;
+    V t = cadd(v[1], v[2]);
+    V u = cscale(csub(v[1], v[2]), s);
+    V a = csub(v[0], cscale(t, (T)0.5));
+    V iu = mul_mi<INV>(u);
+    v[0] = cadd(v[0], t);
+    v[1] = cadd(a, iu);
+    v[2] = csub(a, iu);
+  }
+};
+
+template <bool INV, typename V> struct Dft<5, INV, V> {
+  static __device__ __forceinline__ void run(V *v) {
+    using T = decltype(v[0].x);
+    const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;
+    const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
+    V t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    V u1 = csub(v[1], v[4]), u2 = csub(v[2], v[3]);
+    V a1 = cadd(v[0], cadd(cscale(t1, c1), cscale(t2, c2)));
+    V a2 = cadd(v[0], cadd(cscale(t1, c2), cscale(t2, c1)));
+    V b1 = mul_mi<INV>(cadd(cscale(u1, s1), cscale(u2, s2)));
+    V b2 = mul_mi<INV>(csub(cscale(u1, s2), cscale(u2, s1)));
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
+  }
+};
+
+// ---------------------------------------------------------- line geometry
+
+// Padded index inside a contiguous line: one spare slot every 16 elements,
+// so that the stride-R writes of the early Stockham stages spread over banks.
+__host__ __device__ constexpr int padn(int n) { return n + (n >> 4); }
+__host__ __device__ constexpr int padded_len(int N) { return padn(N - 1) + 1; }
+
+// Lines of a plane / row tile stored row-major: element n of line b at b*P + padn(n).
+template <int NL, int P> struct RowsGeo {
+  static constexpr int nlines = NL;
+  static constexpr bool linefast = false;
+  static __device__ __forceinline__ int at(int b, int n) { return b * P + padn(n); }
+};
+// Columns of a row-major plane: element n of line b (column b) at n*P + padn(b).
+template <int NL, int P> struct ColsGeo {
+  static constexpr int nlines = NL;
+  static constexpr bool linefast = true;
+  static __device__ __forceinline__ int at(int b, int n) { return n * P + padn(b); }
+};
+
+// ----------------------------------------------------------------- stages
+
+template <typename T, int N, int R, int NS, bool INV, class G, int NT>
+__device__ __forceinline__ void tstage(C<T> *buf, const C<T> *tw) {
+  constexpr int NR = N / R;
+  constexpr int total = G::nlines * NR;
+  constexpr int CAPQ = (total + NT - 1) / NT;
+  constexpr int twstep = N / (NS * R);
+  const int tid = threadIdx.x;
+  C<T> v[CAPQ][R];
+  int jq[CAPQ], bq[CAPQ];
+#pragma unroll
+  for (int q = 0; q < CAPQ; ++q) {
+    const int f = tid + q * NT;
+    if (total % NT == 0 || f < total) {
+      int j, b;
+      if constexpr (G::linefast) { b = f % G::nlines; j = f / G::nlines; }
+      else { j = f % NR; b = f / NR; }
+      jq[q] = j;
+      bq[q] = b;
+      const int kk = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C<T> x = buf[G::at(b, j + r * NR)];
+        if constexpr (NS > 1) {
+          if (r > 0) {
+            C<T> w = tw[r * kk * twstep];
+            if (INV) w.y = -w.y;
+            x = cmul(x, w);
+          }
+        }
+        v[q][r] = x;
+      }
+      Dft<R, INV, C<T>>::run(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < CAPQ; ++q) {
+    if (total % NT == 0 || tid + q * NT < total) {
+      const int j = jq[q], b = bq[q];
+      const int kk = j % NS;
+      const int base = (j - kk) * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[G::at(b, base + r * NS)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, bool INV, class G, int NT, int S, int NS>
+__device__ __forceinline__ void run_stages(C<T> *buf, const C<T> *tw) {
+  constexpr RPlan P = make_rplan(N);
+  if constexpr (S < P.n) {
+    constexpr int R = P.r[S];
+    tstage<T, N, R, NS, INV, G, NT>(buf, tw);
+    run_stages<T, N, INV, G, NT, S + 1, NS * R>(buf, tw);
+  }
+}
+
+template <typename T, int N, bool INV, class G, int NT>
+__device__ __forceinline__ void fft_lines_t(C<T> *buf, const C<T> *tw) {
+  run_stages<T, N, INV, G, NT, 0, 1>(buf, tw);
+}
+
+}  // namespace qf

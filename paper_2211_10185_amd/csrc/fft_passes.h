@@ -1,0 +1,257 @@
+// Transform passes of the split-operator step (templates; instantiated per N).
+//
+// One step of an FFT kinetic term (Sec. 2, eqs. HK1-HK3, with the symmetric
+// split h F^-1[e^{-dt T} F[h psi]]) is carried out as passes over HBM, each
+// reading and writing the state once:
+//
+//   plane pass  (x2-x3 plane in LDS): inverse x2,x3 -> x h^2 -> forward x3,x2
+//   row pass    (x3 rows in LDS):     inverse x3 -> x h^2 -> forward x3
+//   column pass (TC contiguous x3 columns along x1 or x2 in LDS):
+//               forward -> x e^{-dt T(k)}/N^3 -> inverse
+//
+// Mode bits (common.h) select which of these pieces a launch performs, so
+// the same kernels also start and end a chunk (x h instead of x h^2) and run
+// plain forward/inverse transforms.
+#pragma once
+
+#include "fft_core.h"
+
+namespace qf {
+
+template <int N> __host__ __device__ constexpr int plane_threads() {
+  int t = (N * N / 16 + 63) / 64 * 64;
+  return t < 64 ? 64 : (t > 1024 ? 1024 : t);
+}
+template <typename T, int N> __host__ __device__ constexpr size_t plane_lds_t() {
+  return (size_t)(N * padded_len(N) + N) * sizeof(C<T>);
+}
+template <typename T, int N> __host__ __device__ constexpr bool plane_fits() {
+  return plane_lds_t<T, N>() <= 160 * 1024 && N * N <= 16 * 1024;
+}
+template <int N> __host__ __device__ constexpr int row_block_t() {
+  int rb = 4096 / N;
+  return rb < 1 ? 1 : rb;
+}
+template <typename T, int N> __host__ __device__ constexpr size_t row_lds_t() {
+  return (size_t)(row_block_t<N>() * padded_len(N) + N) * sizeof(C<T>);
+}
+template <typename T> __host__ __device__ constexpr int col_tile_t() { return sizeof(T) == 4 ? 16 : 8; }
+template <typename T, int N> __host__ __device__ constexpr size_t col_lds_t() {
+  return (size_t)(N * (col_tile_t<T>() + 1) + N) * sizeof(C<T>);
+}
+
+// psi * f where f is real (T) or complex (C<T>) at site `off`.
+template <typename T>
+__device__ __forceinline__ C<T> vmul_t(C<T> v, const void *f, int vcomplex, size_t off) {
+  if (vcomplex) return cmul(v, ((const C<T> *)f)[off]);
+  return cscale(v, ((const T *)f)[off]);
+}
+
+// e^{-dt T(k)} / N^3 at FFT indices (i1, i2, i3).
+template <typename T>
+__device__ __forceinline__ T kin_factor_t(const PassDesc &d, int i1, int i2, int i3) {
+  const T *kt = (const T *)d.ktab;
+  if (d.kin == KIN_REL) {
+    const T p2 = kt[i1] + kt[i2] + kt[i3];
+    const T m = (T)d.m;
+    const T tk = p2 / (sqrt(p2 + m * m) + m);   // sqrt(p^2 + m^2) - m without cancellation
+    return exp(-(T)d.dt * tk) * (T)d.inv_n3;
+  }
+  return kt[i1] * kt[i2] * kt[i3] * (T)d.inv_n3;
+}
+
+template <typename T, int N, int NT>
+__device__ __forceinline__ void load_tw(C<T> *tw, const PassDesc &d) {
+  const C<T> *src = (const C<T> *)d.tw;
+  for (int i = threadIdx.x; i < N; i += NT) tw[i] = src[i];
+}
+
+// ------------------------------------------------------------- plane pass
+
+// Tile = one x2-x3 plane (state s, i1).
+template <typename T, int N>
+__global__ void __launch_bounds__(plane_threads<N>()) k_plane_t(const LaunchList L) {
+  constexpr int NT = plane_threads<N>();
+  constexpr int P = padded_len(N);
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const int t = blockIdx.x - L.tile_start[e];
+  const int s = t / N, i1 = t - s * N;
+  C<T> *pl = (C<T> *)smem;
+  C<T> *tw = pl + N * P;
+  load_tw<T, N, NT>(tw, d);
+  constexpr size_t N2 = (size_t)N * N;
+  C<T> *g = (C<T> *)d.psi + ((size_t)s * N + i1) * N2;
+  const size_t voff = (size_t)i1 * N2;
+  for (int idx = threadIdx.x; idx < N * N; idx += NT) {
+    const int r = idx / N, c = idx - r * N;
+    C<T> v = g[idx];
+    if (mode & M_PRE) v = vmul_t<T>(v, d.hfac, d.vcomplex, voff + idx);
+    pl[r * P + padn(c)] = v;
+  }
+  __syncthreads();
+  using Rows = RowsGeo<N, P>;
+  using Cols = ColsGeo<N, P>;
+  if (mode & M_INV) {
+    fft_lines_t<T, N, true, Cols, NT>(pl, tw);
+    fft_lines_t<T, N, true, Rows, NT>(pl, tw);
+  }
+  if (mode & M_MID) {
+    for (int idx = threadIdx.x; idx < N * N; idx += NT) {
+      const int r = idx / N, c = idx - r * N;
+      const int a = r * P + padn(c);
+      pl[a] = vmul_t<T>(pl[a], d.h2fac, d.vcomplex, voff + idx);
+    }
+    __syncthreads();
+  }
+  if (mode & M_FWD) {
+    fft_lines_t<T, N, false, Rows, NT>(pl, tw);
+    fft_lines_t<T, N, false, Cols, NT>(pl, tw);
+  }
+  for (int idx = threadIdx.x; idx < N * N; idx += NT) {
+    const int r = idx / N, c = idx - r * N;
+    C<T> v = pl[r * P + padn(c)];
+    if (mode & M_POST) v = vmul_t<T>(v, d.hfac, d.vcomplex, voff + idx);
+    g[idx] = v;
+  }
+}
+
+// --------------------------------------------------------------- row pass
+
+// Tile = RB consecutive x3 rows over all states (the last tile may be short).
+template <typename T, int N>
+__global__ void __launch_bounds__(LINE_THREADS) k_row_t(const LaunchList L) {
+  constexpr int NT = LINE_THREADS;
+  constexpr int P = padded_len(N);
+  constexpr int RB = row_block_t<N>();
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const int t = blockIdx.x - L.tile_start[e];
+  const long long rows_total = (long long)d.k * N * N;
+  const long long row0 = (long long)t * RB;
+  const int nrows = (int)((rows_total - row0) < RB ? (rows_total - row0) : RB);
+  C<T> *buf = (C<T> *)smem;
+  C<T> *tw = buf + RB * P;
+  load_tw<T, N, NT>(tw, d);
+  constexpr size_t N3 = (size_t)N * N * N;
+  C<T> *g = (C<T> *)d.psi + (size_t)row0 * N;
+  // site offset of the tile's first row within its state; (voff0 + idx) % N^3 wraps at state boundaries
+  const size_t voff0 = (size_t)(row0 % (long long)(N * N)) * N;
+  for (int idx = threadIdx.x; idx < RB * N; idx += NT) {
+    const int r = idx / N, c = idx - r * N;
+    C<T> v = mkc<T>(0, 0);
+    if (r < nrows) {
+      v = g[idx];
+      if (mode & M_PRE) v = vmul_t<T>(v, d.hfac, d.vcomplex, (voff0 + idx) % N3);
+    }
+    buf[r * P + padn(c)] = v;
+  }
+  __syncthreads();
+  using Rows = RowsGeo<RB, P>;
+  if (mode & M_INV) fft_lines_t<T, N, true, Rows, NT>(buf, tw);
+  if (mode & M_MID) {
+    for (int idx = threadIdx.x; idx < nrows * N; idx += NT) {
+      const int r = idx / N, c = idx - r * N;
+      const int a = r * P + padn(c);
+      buf[a] = vmul_t<T>(buf[a], d.h2fac, d.vcomplex, (voff0 + idx) % N3);
+    }
+    __syncthreads();
+  }
+  if (mode & M_FWD) fft_lines_t<T, N, false, Rows, NT>(buf, tw);
+  for (int idx = threadIdx.x; idx < nrows * N; idx += NT) {
+    const int r = idx / N, c = idx - r * N;
+    C<T> v = buf[r * P + padn(c)];
+    if (mode & M_POST) v = vmul_t<T>(v, d.hfac, d.vcomplex, (voff0 + idx) % N3);
+    g[idx] = v;
+  }
+}
+
+// ------------------------------------------------------------ column pass
+
+template <int NL, int PC> struct TileGeo {
+  static constexpr int nlines = NL;
+  static constexpr bool linefast = true;
+  static __device__ __forceinline__ int at(int b, int n) { return n * PC + b; }
+};
+
+// Tile = TC contiguous x3 columns at one position of the other transverse
+// axis; all N elements along the transform axis (x1 if M_AXIS1, else x2).
+template <typename T, int N>
+__global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
+  constexpr int NT = LINE_THREADS;
+  constexpr int TC = col_tile_t<T>();
+  constexpr int PC = TC + 1;
+  constexpr int NCB = (N + TC - 1) / TC;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const int t = blockIdx.x - L.tile_start[e];
+  constexpr int per_state = N * NCB;
+  const int s = t / per_state;
+  const int rem = t - s * per_state;
+  const int o = rem / NCB, cb = rem - o * NCB;
+  const bool ax1 = (mode & M_AXIS1) != 0;
+  const size_t S = ax1 ? (size_t)N * N : (size_t)N;
+  const size_t OS = ax1 ? (size_t)N : (size_t)N * N;
+  const int c0 = cb * TC;
+  C<T> *buf = (C<T> *)smem;
+  C<T> *tw = buf + N * PC;
+  load_tw<T, N, NT>(tw, d);
+  C<T> *g = (C<T> *)d.psi + (size_t)s * N * N * N + (size_t)o * OS + c0;
+  for (int idx = threadIdx.x; idx < N * TC; idx += NT) {
+    const int n = idx / TC, c = idx - n * TC;
+    C<T> v = mkc<T>(0, 0);
+    if (N % TC == 0 || c0 + c < N) v = g[(size_t)n * S + c];
+    buf[n * PC + c] = v;
+  }
+  __syncthreads();
+  using Geo = TileGeo<TC, PC>;
+  if (mode & M_FWD) fft_lines_t<T, N, false, Geo, NT>(buf, tw);
+  if (mode & M_KIN) {
+    for (int idx = threadIdx.x; idx < N * TC; idx += NT) {
+      const int n = idx / TC, c = idx - n * TC;
+      const int i1 = ax1 ? n : o, i2 = ax1 ? o : n;
+      const int i3 = (N % TC == 0 || c0 + c < N) ? c0 + c : c0;
+      const int a = n * PC + c;
+      buf[a] = cscale(buf[a], kin_factor_t<T>(d, i1, i2, i3));
+    }
+    __syncthreads();
+  }
+  if (mode & M_INV) fft_lines_t<T, N, true, Geo, NT>(buf, tw);
+  const T post = (mode & M_SCALE) ? (T)d.inv_n3 : (T)1;
+  for (int idx = threadIdx.x; idx < N * TC; idx += NT) {
+    const int n = idx / TC, c = idx - n * TC;
+    if (N % TC == 0 || c0 + c < N) g[(size_t)n * S + c] = cscale(buf[n * PC + c], post);
+  }
+}
+
+// ------------------------------------------------------------ dispatch table
+
+
+template <int N> void register_size(FftKernels *tab) {
+  FftKernels &k = tab[N];
+  if constexpr (plane_fits<float, N>()) {
+    k.plane[0] = (const void *)k_plane_t<float, N>;
+    k.plane_lds[0] = plane_lds_t<float, N>();
+  }
+  if constexpr (plane_fits<double, N>()) {
+    k.plane[1] = (const void *)k_plane_t<double, N>;
+    k.plane_lds[1] = plane_lds_t<double, N>();
+  }
+  k.plane_nt = plane_threads<N>();
+  k.row[0] = (const void *)k_row_t<float, N>;
+  k.row[1] = (const void *)k_row_t<double, N>;
+  k.row_lds[0] = row_lds_t<float, N>();
+  k.row_lds[1] = row_lds_t<double, N>();
+  k.col[0] = (const void *)k_col_t<float, N>;
+  k.col[1] = (const void *)k_col_t<double, N>;
+  k.col_lds[0] = col_lds_t<float, N>();
+  k.col_lds[1] = col_lds_t<double, N>();
+}
+
+}  // namespace qf

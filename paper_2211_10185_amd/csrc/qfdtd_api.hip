@@ -11,6 +11,7 @@
 //   H_K^(0): n stencil passes (ping-pong between psi and alt).
 // After every chunk: parity projection (if any sector is set), FP64 Gram
 // matrix, Cholesky per sector, psi <- psi R^{-1}.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,16 +22,11 @@
 #include "qfdtd.h"
 
 namespace qf {
-size_t plane_lds(int N, bool dbl);
-size_t row_lds(int N, bool dbl);
-size_t col_lds(int N, bool dbl);
-int plane_tiles(int N, int k);
-int row_tiles(int N, int k);
-int col_tiles(int N, int k, bool dbl);
-hipError_t fft_kernels_init();
-void launch_plane(const LaunchList &L, int total, size_t lds, bool dbl, hipStream_t st);
-void launch_row(const LaunchList &L, int total, size_t lds, bool dbl, hipStream_t st);
-void launch_col(const LaunchList &L, int total, size_t lds, bool dbl, hipStream_t st);
+void register_fft_group0(FftKernels *t);
+void register_fft_group1(FftKernels *t);
+void register_fft_group2(FftKernels *t);
+void register_fft_group3(FftKernels *t);
+void register_fft_group4(FftKernels *t);
 void launch_tables(bool dbl, void *tw, double2 *tw64, double *ksym64, int N, int kin, double a, double m, hipStream_t st);
 void launch_potential(double *v64, int vcomplex, int N, double a, int kind, const double *p, const double *knots, int nk,
                       const double2 *add, hipStream_t st);
@@ -84,6 +80,42 @@ int make_plan(int N, int32_t *radix) {
   while (n % 5 == 0) { radix[s++] = 5; n /= 5; }
   while (n % 3 == 0) { radix[s++] = 3; n /= 3; }
   return s;
+}
+
+FftKernels g_fft[257];
+
+hipError_t fft_table_init() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  std::memset(g_fft, 0, sizeof(g_fft));
+  register_fft_group0(g_fft);
+  register_fft_group1(g_fft);
+  register_fft_group2(g_fft);
+  register_fft_group3(g_fft);
+  register_fft_group4(g_fft);
+  for (int n = 0; n <= 256; ++n)
+    for (int w = 0; w < 2; ++w) {
+      const void *fs[3] = {g_fft[n].plane[w], g_fft[n].row[w], g_fft[n].col[w]};
+      const size_t ls[3] = {g_fft[n].plane_lds[w], g_fft[n].row_lds[w], g_fft[n].col_lds[w]};
+      for (int q = 0; q < 3; ++q)
+        if (fs[q]) {
+          hipError_t e = hipFuncSetAttribute(fs[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ls[q]);
+          if (e != hipSuccess) return e;
+        }
+    }
+  done = true;
+  return hipSuccess;
+}
+
+int plane_tiles(int N, int k) { return k * N; }
+int row_tiles(int N, int k) {
+  const long long rows = (long long)k * N * N;
+  const int rb = (4096 / N) < 1 ? 1 : 4096 / N;
+  return (int)((rows + rb - 1) / rb);
+}
+int col_tiles(int N, int k, bool dbl) {
+  const int tc = dbl ? 8 : 16;
+  return k * N * ((N + tc - 1) / tc);
 }
 
 }  // namespace
@@ -159,6 +191,12 @@ qfdtd_status fail(qfdtd_ctx *c, qfdtd_status s, const std::string &msg) {
     if (e_ != hipSuccess) return fail(c, QFDTD_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
   } while (0)
 
+#define QF_TRY(x)                          \
+  do {                                     \
+    qfdtd_status s_ = (x);                 \
+    if (s_ != QFDTD_OK) return s_;         \
+  } while (0)
+
 // ------------------------------------------------------------- timing
 
 int tbegin(qfdtd_ctx *c, int cls, double bytes) {
@@ -224,8 +262,25 @@ double entry_bytes(const Entry &e, Fam f) {
   }
 }
 
-qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS = 0) {
+qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS = 0);
+
+// transform passes are instantiated per lattice size: one launch per distinct N
+qfdtd_status run_fft_family(Fam f, std::vector<Entry> &es, bool dbl) {
+  std::vector<int> sizes;
+  for (auto &e : es)
+    if (std::find(sizes.begin(), sizes.end(), e.c->N) == sizes.end()) sizes.push_back(e.c->N);
+  for (int N : sizes) {
+    std::vector<Entry> sub;
+    for (auto &e : es)
+      if (e.c->N == N) sub.push_back(e);
+    QF_TRY(run_family(f, sub, dbl, -1));
+  }
+  return QFDTD_OK;
+}
+
+qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS) {
   if (es.empty()) return QFDTD_OK;
+  if ((f == F_PLANE || f == F_ROW || f == F_COL) && KS != -1) return run_fft_family(f, es, dbl);
   qfdtd_ctx *c0 = es[0].c;
   hipStream_t st = c0->st;
   for (size_t base = 0; base < es.size(); base += MAX_LAUNCH) {
@@ -242,11 +297,11 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS = 0) {
       L.mode[i] = (uint16_t)e.mode;
       L.aux[i] = e.aux;
       total += e.tiles;
-      const int N = e.c->N;
+      const FftKernels &K = g_fft[e.c->N];
       size_t l = 0;
-      if (f == F_PLANE) l = plane_lds(N, dbl);
-      else if (f == F_ROW) l = row_lds(N, dbl);
-      else if (f == F_COL) l = col_lds(N, dbl);
+      if (f == F_PLANE) l = K.plane_lds[dbl];
+      else if (f == F_ROW) l = K.row_lds[dbl];
+      else if (f == F_COL) l = K.col_lds[dbl];
       if (l > lds) lds = l;
       bytes += entry_bytes(e, f);
     }
@@ -258,10 +313,14 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS = 0) {
     else if (f == F_COL) cls = TC_COL;
     else if (f == F_STENCIL) cls = TC_STENCIL;
     const int tix = cls >= 0 ? tbegin(c0, cls, bytes) : -1;
+    const FftKernels &K = g_fft[es[base].c->N];
+    void *kargs[] = {(void *)&L};
     switch (f) {
-      case F_PLANE: launch_plane(L, total, lds, dbl, st); break;
-      case F_ROW: launch_row(L, total, lds, dbl, st); break;
-      case F_COL: launch_col(L, total, lds, dbl, st); break;
+      case F_PLANE:
+        (void)hipLaunchKernel(K.plane[dbl], dim3(total), dim3(K.plane_nt), kargs, lds, st);
+        break;
+      case F_ROW: (void)hipLaunchKernel(K.row[dbl], dim3(total), dim3(LINE_THREADS), kargs, lds, st); break;
+      case F_COL: (void)hipLaunchKernel(K.col[dbl], dim3(total), dim3(LINE_THREADS), kargs, lds, st); break;
       case F_STENCIL: launch_stencil(L, total, dbl, st); break;
       case F_PARITY: launch_parity(L, total, dbl, st); break;
       case F_TO64: launch_to64(L, total, dbl, st); break;
@@ -278,11 +337,6 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS = 0) {
   return QFDTD_OK;
 }
 
-#define QF_TRY(x)                          \
-  do {                                     \
-    qfdtd_status s_ = (x);                 \
-    if (s_ != QFDTD_OK) return s_;         \
-  } while (0)
 
 // run a family separately for each distinct k (kernels templated on k)
 qfdtd_status run_by_k(Fam f, std::vector<Entry> &es, bool dbl) {
@@ -439,7 +493,7 @@ qfdtd_status set_dt(qfdtd_ctx *c, double dt) {
 }
 
 qfdtd_status check_status(qfdtd_ctx *c, bool wait) {
-  if (!c->status_pending) return c->poisoned ? QFDTD_E_NUMERIC : QFDTD_OK;
+  if (!c->status_pending) return QFDTD_OK;
   if (wait) QF_HIP(c, hipEventSynchronize(c->status_ev));
   else if (hipEventQuery(c->status_ev) != hipSuccess) return QFDTD_OK;
   c->status_pending = false;
@@ -562,11 +616,9 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   }
   for (int i = 0; i < o.n_states && o.sectors; ++i)
     if (o.sectors[i] < 0 || o.sectors[i] > 5) return fail(nullptr, QFDTD_E_INVALID, "sector must be 0..5");
-  static bool inited = false;
-  if (!inited) {
-    hipError_t e = fft_kernels_init();
+  {
+    hipError_t e = fft_table_init();
     if (e != hipSuccess) return fail(nullptr, QFDTD_E_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
-    inited = true;
   }
   qfdtd_ctx *c = new qfdtd_ctx();
   c->N = N; c->a = a; c->m = m; c->kin = kinetic;
@@ -587,8 +639,12 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     for (size_t g = 0; g < n3; ++g)
       if (V->grid[2 * g + 1] != 0.0) { c->vcomplex = true; break; }
   }
-  c->plane = c->fft() && plane_lds(N, c->dbl) <= 160 * 1024 && (size_t)N * N <= 16 * PLANE_THREADS;
-  c->plane64 = c->fft() && plane_lds(N, true) <= 160 * 1024 && (size_t)N * N <= 16 * PLANE_THREADS;
+  if (c->fft() && !g_fft[N].col[0]) {
+    delete c;
+    return fail(nullptr, QFDTD_E_UNSUPPORTED_N, "no transform kernels for this N");
+  }
+  c->plane = c->fft() && g_fft[N].plane[c->dbl ? 1 : 0] != nullptr;
+  c->plane64 = c->fft() && g_fft[N].plane[1] != nullptr;
   c->nblk_red = (int)((n3 + 2047) / 2048);
   if (c->nblk_red > 1024) c->nblk_red = 1024;
   if (c->nblk_red < 1) c->nblk_red = 1;

@@ -1,0 +1,239 @@
+"""GPU system tests: batches, failure handling, determinism, full-size configs."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from compare import energy_errors, phase_aligned_l2, wavefunction_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def solver(p, **kw):
+    from paper_2211_10185_amd.solver import Solver
+    return Solver.from_problem(p, **kw)
+
+
+def prob(kinetic, N, prec=0, k=3, a=0.25, m=1.0, vkind=S.V_HARMONIC, vparams=(1.0,), sectors=None,
+         K=50, dt=None, seed=5, vgrid_seed=None):
+    return S.Problem(N=N, a=a, m=m, kinetic=kinetic, vkind=vkind, vparams=vparams, k=k, sectors=sectors,
+                     precision=prec, dt=a * a / 8 if dt is None else dt, steps=0, measure_every=K,
+                     seed=seed, vgrid_seed=vgrid_seed)
+
+
+def test_batch_equals_alone_bitwise():
+    from paper_2211_10185_amd.solver import batch_evolve
+    probs = [prob(S.K_NR_SIN2, 48, seed=1), prob(S.K_REL, 160, k=2, a=0.05, m=2.0, vkind=S.V_CORNELL,
+                                                  vparams=(0.3, 0.2, 0.025), K=5, dt=0.05 / 8, seed=2),
+             prob(S.K_NR_P2, 64, seed=3), prob(S.K_FDTD, 40, seed=4), prob(S.K_NR_SIN2, 48, seed=6, K=7)]
+    steps = [60, 12, 75, 33, 41]
+    alone = []
+    for p, n in zip(probs, steps):
+        s = solver(p)
+        s.set_states(p.init_states())
+        s.evolve(n, p.dt)
+        alone.append(s.states())
+        s.close()
+    ss = [solver(p) for p in probs]
+    for s, p in zip(ss, probs):
+        s.set_states(p.init_states())
+    batch_evolve(ss, steps, [p.dt for p in probs])
+    for s, (Ea, psia) in zip(ss, alone):
+        Eb, psib = s.states()
+        assert np.array_equal(Ea, Eb)
+        assert np.array_equal(psia, psib)
+        s.close()
+
+
+def test_repeat_runs_are_bitwise_identical_and_resume_matches():
+    p = prob(S.K_REL, 40, a=0.05, m=1.5, vkind=S.V_CORNELL, vparams=(0.4, 0.2, 0.025), dt=0.05 / 8,
+             sectors=(S.S_PLUS, S.S_PLUS, S.S_PK3), vgrid_seed=3)
+    outs = []
+    for _ in range(2):
+        s = solver(p)
+        s.set_states(p.init_states())
+        s.evolve(100, p.dt)
+        outs.append(s.states())
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    # checkpoint after 50 steps, resume in a fresh context: equal to the oracle's 100-step run
+    s = solver(p, precision=1)
+    s.set_states(p.init_states())
+    s.evolve(50, p.dt)
+    _, ck = s.states()
+    s.close()
+    s2 = solver(p, precision=1)
+    s2.set_states(ck)
+    s2.evolve(50, p.dt)
+    E, psi = s2.states()
+    s2.close()
+    ref = O.solve(p, steps=100)
+    assert np.max(energy_errors(E, ref["energies"])) < 1e-10
+    for i in range(3):
+        assert phase_aligned_l2(psi[i], ref["states"][i]) < 1e-9
+
+
+def test_states_roundtrip_without_steps_is_projected_gram_schmidt():
+    p = prob(S.K_NR_P2, 24, prec=1, sectors=(S.S_PLUS, S.S_MINUS, S.S_PLUS))
+    init = p.init_states()
+    s = solver(p)
+    s.set_states(init)
+    E, psi = s.states()
+    s.close()
+    ref = O.prepare(init, [S.S_PLUS, S.S_MINUS, S.S_PLUS], True)
+    for i in range(3):
+        assert np.max(np.abs(psi[i] - ref[i])) < 1e-12
+    Er = O.energies(ref, p.kinetic, p.a, p.m, O.problem_potential(p))
+    assert np.max(np.abs(E - Er)) < 1e-10 * np.max(np.abs(Er))
+
+
+def test_energy_trace_rows_per_chunk():
+    p = prob(S.K_NR_SIN2, 32, K=20)
+    s = solver(p, trace=True)
+    s.set_states(p.init_states())
+    s.evolve(130, p.dt)
+    tr = s.energy_trace()
+    E = s.energies()
+    s.close()
+    assert tr.shape == (7, 3)
+    assert np.allclose(tr[-1], E, rtol=0, atol=1e-12)
+    ref = []
+    O.evolve(O.prepare(p.init_states(), [0, 0, 0], True), p.kinetic, p.a, p.m, O.problem_potential(p),
+             p.dt, 130, 20, [0, 0, 0], trace=ref)
+    assert np.max(np.abs(tr - np.array(ref)) / np.abs(np.array(ref))) < 1e-5
+
+
+def test_unstable_fdtd_dt_is_rejected():
+    from paper_2211_10185_amd._lib import QfdtdError, E_UNSTABLE_DT
+    p = prob(S.K_FDTD, 16, k=1)
+    s = solver(p)
+    s.set_states(p.init_states())
+    with pytest.raises(QfdtdError) as ei:
+        s.evolve(10, p.m * p.a ** 2 / 3 * 1.01)
+    assert ei.value.status == E_UNSTABLE_DT
+    s.evolve(10, p.m * p.a ** 2 / 3)       # at the bound: accepted
+    s.close()
+
+
+def test_nan_state_poisons_context_until_reset():
+    from paper_2211_10185_amd._lib import QfdtdError, E_NUMERIC, E_STATE
+    p = prob(S.K_NR_SIN2, 16, k=2)
+    s = solver(p)
+    bad = p.init_states()
+    bad[1, 3, 4, 5] = np.nan
+    s.set_states(bad)
+    with pytest.raises(QfdtdError) as ei:
+        s.evolve(20, p.dt)
+        s.energies()
+    assert ei.value.status == E_NUMERIC
+    with pytest.raises(QfdtdError) as ei:
+        s.evolve(20, p.dt)
+    assert ei.value.status == E_STATE
+    good = p.init_states()
+    s.set_states(good)
+    s.evolve(20, p.dt)
+    E = s.energies()
+    assert np.all(np.isfinite(E))
+    s.close()
+
+
+# ------------------------------------------------------------ full sizes
+
+def separable_levels(kind, N, a, m):
+    x = O.coords(N, a)
+    if kind == S.K_NR_SIN2:
+        D = -2 * np.eye(N) + np.eye(N, k=1) + np.eye(N, k=-1)
+        D[0, -1] = D[-1, 0] = 1
+    else:
+        D = -2 * np.eye(N) + np.eye(N, k=1) + np.eye(N, k=-1)
+    return -D / (2 * m * a * a), np.diag(0.5 * x * x)
+
+
+@pytest.mark.parametrize("kind", [S.K_NR_SIN2, S.K_FDTD])
+def test_config2_full_run_reaches_lattice_spectrum(kind):
+    p = S.config2(kind)
+    s = solver(p)
+    s.set_states(p.init_states())
+    s.evolve(p.steps, p.dt)
+    E, psi = s.states()
+    s.close()
+    K1, V1 = separable_levels(kind, p.N, p.a, p.m)
+    if kind == S.K_NR_SIN2:
+        ev = np.linalg.eigvalsh(K1 + V1)
+        ref0, ref1 = 3 * ev[0], 2 * ev[0] + ev[1]
+        tol = 1e-5
+    else:
+        # fixed point of the A/B step: (K + c V) w = eps/3 w, c = 1 - dt eps / 2
+        c = 1.0
+        for _ in range(100):
+            w_e, w_U = np.linalg.eigh(K1 + c * V1)
+            c = 1 - p.dt * 3 * w_e[0] / 2
+        w = w_U[:, 0]
+        ref0 = 3 * (w @ (K1 + V1) @ w)
+        ev = np.linalg.eigvalsh(K1 + V1)
+        ref1 = 2 * ev[0] + ev[1]
+        tol = 1e-5
+    assert abs(E[0].real - ref0) / abs(ref0) < 1e-5, (E, ref0)
+    # excited pair: the A/B scheme's excited Schur vectors are pinned to O(dt^2) only
+    assert np.all(np.abs(E[1:].real - ref1) / ref1 < (tol if kind == S.K_NR_SIN2 else 5e-5)), (E, ref1)
+    G = np.array([[np.vdot(a_.ravel(), b_.ravel()) for b_ in psi] for a_ in psi])
+    assert np.max(np.abs(G - np.eye(3))) < 1e-5
+
+
+@pytest.mark.parametrize("kind", [S.K_NR_SIN2, S.K_FDTD])
+def test_config2_full_size_short_run_matches_oracle(kind):
+    p = S.config2(kind)
+    p.measure_every = 5
+    E, psi = None, None
+    s = solver(p)
+    init = p.init_states()
+    s.set_states(init)
+    s.evolve(12, p.dt)
+    E, psi = s.states()
+    s.close()
+    ref = O.solve(p, steps=12, init=init)
+    assert np.max(energy_errors(E, ref["energies"])) < 1e-5
+    assert np.max(wavefunction_errors(psi, ref["states"], ref["energies"])) < 1e-4
+
+
+def test_config3_full_size_short_run_matches_oracle():
+    p = S.config3()
+    p.measure_every = 2
+    init = p.init_states()
+    s = solver(p)
+    s.set_states(init)
+    s.evolve(4, p.dt)
+    E, psi = s.states()
+    s.close()
+    ref = O.solve(p, steps=4, init=init)
+    assert np.max(energy_errors(E, ref["energies"])) < 1e-5, (E, ref["energies"])
+    assert np.max(wavefunction_errors(psi, ref["states"], ref["energies"])) < 1e-4
+
+
+def test_config3_full_run_properties():
+    p = S.config3()
+    s = solver(p, trace=True)
+    s.set_states(p.init_states())
+    s.evolve(p.steps, p.dt)
+    E, psi = s.states()
+    tr = s.energy_trace()
+    s.close()
+    assert np.all(np.isfinite(E))
+    # Im <psi|H|psi> = <psi|Im V|psi> for a normalised state, and 0 <= Im V < 0.01
+    assert np.all(E.imag >= 0) and np.all(E.imag <= 0.01)
+    assert E[0].real < E[1].real            # 1S below 2S in the P+ sector
+    G = np.array([[np.vdot(a_.ravel(), b_.ravel()) for b_ in psi] for a_ in psi])
+    assert np.max(np.abs(G[:2, :2] - np.eye(2))) < 1e-5 and abs(G[2, 2] - 1) < 1e-5
+    # sector symmetries under x -> -x about site N/2 (periodic): i -> (N - i) mod N
+    def refl(f, axes):
+        for ax in axes:
+            f = np.roll(np.flip(f, axis=ax), 1, axis=ax)
+        return f
+    for i in (0, 1):
+        assert np.linalg.norm(refl(psi[i], (0, 1, 2)) - psi[i]) < 1e-4
+    assert np.linalg.norm(refl(psi[2], (0, 1)) - psi[2]) < 1e-4
+    assert np.linalg.norm(refl(psi[2], (2,)) + psi[2]) < 1e-4
+    # the chunk trace has settled
+    assert np.max(np.abs(tr[-1] - tr[-2])) < 1e-6
