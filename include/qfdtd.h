@@ -112,7 +112,12 @@ typedef struct {
   qfdtd_alloc_fn dev_alloc;   /* optional device allocator (e.g. a framework caching allocator) */
   qfdtd_free_fn dev_free;     /* must be given together with dev_alloc */
   void *alloc_user;           /* passed to dev_alloc / dev_free */
+  uint32_t flags;             /* QFDTD_F_* bits */
 } qfdtd_options;
+
+/* qfdtd_options.flags */
+#define QFDTD_F_SINGLE_STREAM 1u  /* do not split the states of an FFT solve into two
+                                     groups evolved on two internal streams */
 
 typedef struct qfdtd_ctx qfdtd_ctx;
 

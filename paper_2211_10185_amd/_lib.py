@@ -35,7 +35,10 @@ class Options(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("n_states", ct.c_int32),
                 ("sectors", ct.POINTER(ct.c_int32)), ("measure_every", ct.c_int32),
                 ("trace_energies", ct.c_int32), ("hip_stream", ct.c_void_p),
-                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ct.c_void_p)]
+                ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_user", ct.c_void_p),
+                ("flags", ct.c_uint32)]
+
+F_SINGLE_STREAM = 1
 
 
 class QfdtdError(RuntimeError):

@@ -120,50 +120,100 @@ __global__ void k_dt_tables(const double *v64, int vcomplex, size_t N3, double d
 
 // psi' = A psi + B c (sum of 6 neighbours - 6 psi), c = dt/(2 m a^2),
 // A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2); walls are ghost zeros.
+//
+// Tile = 64 (x3) x 4 (x2) columns of one state over a chunk of ST_CZ planes
+// along x1.  Each thread marches along x1 keeping psi at i1-1, i1, i1+1 in
+// registers, so every site is read once from memory per sweep; the four
+// in-plane neighbours are the centres of neighbouring lanes and rows (L1).
+constexpr int ST_TX = 64, ST_TY = RED_THREADS / 64, ST_CZ = 16;
+
+__host__ __device__ inline int stencil_tiles(int N, int k) {
+  return k * ((N + ST_TX - 1) / ST_TX) * ((N + ST_TY - 1) / ST_TY) * ((N + ST_CZ - 1) / ST_CZ);
+}
+
+template <typename T, bool VC>
+__device__ __forceinline__ C<T> fdtd_update(C<T> cur, C<T> acc, const void *__restrict__ vtab, int off, T c, T hdt) {
+  if constexpr (VC) {
+    const C<T> V = ((const C<T> *)vtab)[off];
+    // B = 1/(1 + dt V/2), A = (1 - dt V/2) B
+    const T dr = (T)1 + hdt * V.x, di = hdt * V.y;
+    const T den = (T)1 / (dr * dr + di * di);
+    const C<T> B = mkc<T>(dr * den, -di * den);
+    const C<T> A = cmul(mkc<T>((T)1 - hdt * V.x, -hdt * V.y), B);
+    return cadd(cmul(A, cur), cmul(B, cscale(acc, c)));
+  } else {
+    const T V = ((const T *)vtab)[off];
+    const T B = (T)1 / ((T)1 + hdt * V);
+    const T A = ((T)1 - hdt * V) * B;
+    return cadd(cscale(cur, A), cscale(acc, B * c));
+  }
+}
+
+// z-march over one column; ZU planes per group: all loads of a group are
+// issued before its stores so that each thread keeps several HBM reads in flight
+template <typename T, bool VC>
+__device__ __forceinline__ void stencil_column(const C<T> *__restrict__ sp, C<T> *__restrict__ dp,
+                                               const void *__restrict__ vtab, int N, int i2, int i3, int z0,
+                                               int z1, T c, T hdt) {
+  constexpr int ZU = 8;
+  const int N2 = N * N;
+  const C<T> zero = mkc<T>(0, 0);
+  int off = (z0 * N + i2) * N + i3;
+  C<T> prev = z0 > 0 ? sp[off - N2] : zero;
+  C<T> cur = sp[off];
+  const bool xl = i3 > 0, xr = i3 < N - 1, yl = i2 > 0, yr = i2 < N - 1;
+  for (int z = z0; z < z1; z += ZU) {
+    C<T> nx[ZU], nb[ZU];
+#pragma unroll
+    for (int u = 0; u < ZU; ++u) {
+      const int zz = z + u;
+      const int o = off + u * N2;
+      nx[u] = (zz + 1 < N) ? sp[o + N2] : zero;
+      C<T> a = zero;
+      if (zz < z1) {
+        if (xl) a = cadd(a, sp[o - 1]);
+        if (xr) a = cadd(a, sp[o + 1]);
+        if (yl) a = cadd(a, sp[o - N]);
+        if (yr) a = cadd(a, sp[o + N]);
+      }
+      nb[u] = a;
+    }
+#pragma unroll
+    for (int u = 0; u < ZU; ++u) {
+      if (z + u < z1) {
+        const C<T> acc = cadd(csub(cadd(prev, nx[u]), cscale(cur, (T)6)), nb[u]);
+        dp[off] = fdtd_update<T, VC>(cur, acc, vtab, off, c, hdt);
+        prev = cur;
+        cur = nx[u];
+        off += N2;
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) k_stencil(const LaunchList L) {
   const int e = find_entry(L, blockIdx.x);
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
   const int N = d.N;
+  const int ntx = (N + ST_TX - 1) / ST_TX, nty = (N + ST_TY - 1) / ST_TY, ncz = (N + ST_CZ - 1) / ST_CZ;
+  int t = blockIdx.x - L.tile_start[e];
+  const int bx = t % ntx; t /= ntx;
+  const int by = t % nty; t /= nty;
+  const int bz = t % ncz;
+  const int s = t / ncz;
+  const int i3 = bx * ST_TX + (threadIdx.x & 63);
+  const int i2 = by * ST_TY + (threadIdx.x >> 6);
+  if (i3 >= N || i2 >= N) return;
   const size_t N3 = (size_t)N * N * N;
-  const C<T> *src = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi);
-  C<T> *dst = (C<T> *)((mode & M_SWAP) ? d.psi : d.alt);
+  const C<T> *sp = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi) + (size_t)s * N3;
+  C<T> *dp = (C<T> *)((mode & M_SWAP) ? d.psi : d.alt) + (size_t)s * N3;
   const T c = (T)d.stencil_c, hdt = (T)(0.5 * d.dt);
-  const long long base = (long long)(blockIdx.x - L.tile_start[e]) * RED_THREADS * EW_PER_THREAD;
-  const long long total = (long long)d.k * N3;
-#pragma unroll
-  for (int q = 0; q < EW_PER_THREAD; ++q) {
-    const long long gi = base + q * RED_THREADS + threadIdx.x;
-    if (gi >= total) break;
-    const size_t x = (size_t)(gi % N3);
-    const C<T> *sp = src + (gi - x);
-    const int i3 = (int)(x % N), i2 = (int)((x / N) % N), i1 = (int)(x / ((size_t)N * N));
-    const C<T> v = sp[x];
-    C<T> acc = cscale(v, (T)-6);
-    if (i3 > 0) acc = cadd(acc, sp[x - 1]);
-    if (i3 < N - 1) acc = cadd(acc, sp[x + 1]);
-    if (i2 > 0) acc = cadd(acc, sp[x - N]);
-    if (i2 < N - 1) acc = cadd(acc, sp[x + N]);
-    if (i1 > 0) acc = cadd(acc, sp[x - (size_t)N * N]);
-    if (i1 < N - 1) acc = cadd(acc, sp[x + (size_t)N * N]);
-    C<T> out;
-    if (d.vcomplex) {
-      const C<T> V = ((const C<T> *)d.vtab)[x];
-      // B = 1/(1 + dt V/2), A = (1 - dt V/2) B
-      const T dr = (T)1 + hdt * V.x, di = hdt * V.y;
-      const T den = (T)1 / (dr * dr + di * di);
-      const C<T> B = mkc<T>(dr * den, -di * den);
-      const C<T> A = cmul(mkc<T>((T)1 - hdt * V.x, -hdt * V.y), B);
-      out = cadd(cmul(A, v), cmul(B, cscale(acc, c)));
-    } else {
-      const T V = ((const T *)d.vtab)[x];
-      const T B = (T)1 / ((T)1 + hdt * V);
-      const T A = ((T)1 - hdt * V) * B;
-      out = cadd(cscale(v, A), cscale(acc, B * c));
-    }
-    dst[gi] = out;
-  }
+  const int z0 = bz * ST_CZ;
+  const int z1 = (z0 + ST_CZ < N) ? z0 + ST_CZ : N;
+  if (d.vcomplex) stencil_column<T, true>(sp, dp, d.vtab, N, i2, i3, z0, z1, c, hdt);
+  else stencil_column<T, false>(sp, dp, d.vtab, N, i2, i3, z0, z1, c, hdt);
 }
 
 // ---------------------------------------------------------------- parity
@@ -276,6 +326,24 @@ __global__ void __launch_bounds__(RED_THREADS) k_gram(const LaunchList L) {
 
 __device__ __forceinline__ int pair_index(int i, int j, int KS) { return i * KS - i * (i - 1) / 2 + (j - i); }
 
+// Sum of column q of a [nb][2*MAX_PAIRS] partials array over its nb rows with
+// all threads of the block: strided per-thread sums, then a fixed-shape tree.
+// Every thread returns the same value; the order of additions never changes.
+__device__ double block_sum_column(const double *part, int nb, int q) {
+  __shared__ double red[RED_THREADS];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RED_THREADS) s += part[(size_t)b * (2 * MAX_PAIRS) + q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
 // Sum the partials (fixed order), Cholesky G = R^H R per sector, coef = R^{-1}.
 __global__ void __launch_bounds__(RED_THREADS) k_gram_finalize(const LaunchList L) {
   const int e = blockIdx.x;
@@ -283,10 +351,9 @@ __global__ void __launch_bounds__(RED_THREADS) k_gram_finalize(const LaunchList 
   const int KS = d.k;
   const int NP = KS * (KS + 1) / 2;
   __shared__ double G[MAX_PAIRS * 2];
-  for (int q = threadIdx.x; q < 2 * NP; q += blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < d.nblk_red; ++b) s += d.partials[(size_t)b * (2 * MAX_PAIRS) + q];
-    G[q] = s;
+  for (int q = 0; q < 2 * NP; ++q) {
+    const double v = block_sum_column(d.partials, d.nblk_red, q);
+    if (threadIdx.x == 0) G[q] = v;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -486,15 +553,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_energy_finalize(const LaunchLis
   const int KS = d.k;
   const bool fdtd = d.kin == KIN_FDTD;
   __shared__ double S[6 * MAX_STATES];
-  for (int q = threadIdx.x; q < 6 * KS; q += blockDim.x) {
-    double s = 0.0;
-    if (q < 5 * KS) {
-      for (int b = 0; b < d.nblk_red; ++b) s += d.partials[(size_t)b * (2 * MAX_PAIRS) + q];
-    } else if (!fdtd) {
-      const int st = q - 5 * KS;
-      for (int b = 0; b < d.nblk_red; ++b) s += d.partials[(size_t)(d.nblk_red + b) * (2 * MAX_PAIRS) + st];
-    }
-    S[q] = s;
+  for (int q = 0; q < 6 * KS; ++q) {
+    double v = 0.0;
+    if (q < 5 * KS) v = block_sum_column(d.partials, d.nblk_red, q);
+    else if (!fdtd) v = block_sum_column(d.partials + (size_t)d.nblk_red * (2 * MAX_PAIRS), d.nblk_red, q - 5 * KS);
+    if (threadIdx.x == 0) S[q] = v;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -565,6 +628,7 @@ void launch_to64_slot(bool dbl, double2 *dst, const void *src, size_t n, hipStre
 }
 
 int ew_tiles_host(long long n) { return ew_tiles(n); }
+int stencil_tiles_host(int N, int k) { return stencil_tiles(N, k); }
 
 void launch_stencil(const LaunchList &L, int total, bool dbl, hipStream_t st) {
   if (dbl) hipLaunchKernelGGL(k_stencil<double>, dim3(total), dim3(RED_THREADS), 0, st, L);

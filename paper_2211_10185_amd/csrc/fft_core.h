@@ -186,14 +186,80 @@ template <int NL, int P> struct ColsGeo {
   static __device__ __forceinline__ int at(int b, int n) { return n * P + padn(b); }
 };
 
+// ------------------------------------------------------- twiddle tables
+//
+// Each stage with Ns > 1 gets its own LDS table laid out [r-1][j mod Ns]
+// holding w^{r (j mod Ns) N/(Ns R)}, so that lanes with consecutive j read
+// consecutive entries (a single table indexed r (j mod Ns) N/(Ns R) makes
+// lanes stride through it and collide on LDS banks).  Tables of the radix
+// plan come first, then those of the reversed plan.
+
+template <int N, bool REV> __host__ __device__ constexpr RPlan plan_of() {
+  RPlan p = make_rplan(N);
+  if (REV) {
+    RPlan q = p;
+    for (int i = 0; i < p.n; ++i) q.r[i] = p.r[p.n - 1 - i];
+    return q;
+  }
+  return p;
+}
+template <int N, bool REV, int S> __host__ __device__ constexpr int ns_before() {
+  int ns = 1;
+  for (int i = 0; i < S; ++i) ns *= plan_of<N, REV>().r[i];
+  return ns;
+}
+template <int N, bool REV> __host__ __device__ constexpr int tw_plan_size() {
+  constexpr RPlan p = plan_of<N, REV>();
+  int sz = 0, ns = 1;
+  for (int i = 0; i < p.n; ++i) {
+    if (ns > 1) sz += (p.r[i] - 1) * ns;
+    ns *= p.r[i];
+  }
+  return sz;
+}
+template <int N> __host__ __device__ constexpr int tw_total() { return tw_plan_size<N, false>() + tw_plan_size<N, true>(); }
+template <int N, bool REV, int S> __host__ __device__ constexpr int tw_off() {
+  constexpr RPlan p = plan_of<N, REV>();
+  int off = REV ? tw_plan_size<N, false>() : 0, ns = 1;
+  for (int i = 0; i < S; ++i) {
+    if (ns > 1) off += (p.r[i] - 1) * ns;
+    ns *= p.r[i];
+  }
+  return off;
+}
+
+template <typename T, int N, bool REV, int NT, int S>
+__device__ __forceinline__ void fill_tw_plan(C<T> *lt, const C<T> *gtw) {
+  constexpr RPlan p = plan_of<N, REV>();
+  if constexpr (S < p.n) {
+    constexpr int R = p.r[S];
+    constexpr int NS = ns_before<N, REV, S>();
+    if constexpr (NS > 1) {
+      constexpr int off = tw_off<N, REV, S>();
+      constexpr int twstep = N / (NS * R);
+      for (int i = threadIdx.x; i < (R - 1) * NS; i += NT) {
+        const int r = i / NS + 1, kk = i - (r - 1) * NS;
+        lt[off + i] = gtw[r * kk * twstep];
+      }
+    }
+    fill_tw_plan<T, N, REV, NT, S + 1>(lt, gtw);
+  }
+}
+
+// stage twiddle tables of both plans from the roots of unity w^m, m < N (global)
+template <typename T, int N, int NT>
+__device__ __forceinline__ void fill_twiddles(C<T> *lt, const C<T> *gtw) {
+  fill_tw_plan<T, N, false, NT, 0>(lt, gtw);
+  fill_tw_plan<T, N, true, NT, 0>(lt, gtw);
+}
+
 // ----------------------------------------------------------------- stages
 
-template <typename T, int N, int R, int NS, bool INV, class G, int NT>
+template <typename T, int N, int R, int NS, bool INV, class G, int NT, int TWOFF>
 __device__ __forceinline__ void tstage(C<T> *buf, const C<T> *tw) {
   constexpr int NR = N / R;
   constexpr int total = G::nlines * NR;
   constexpr int CAPQ = (total + NT - 1) / NT;
-  constexpr int twstep = N / (NS * R);
   const int tid = threadIdx.x;
   C<T> v[CAPQ][R];
   int jq[CAPQ], bq[CAPQ];
@@ -212,7 +278,7 @@ __device__ __forceinline__ void tstage(C<T> *buf, const C<T> *tw) {
         C<T> x = buf[G::at(b, j + r * NR)];
         if constexpr (NS > 1) {
           if (r > 0) {
-            C<T> w = tw[r * kk * twstep];
+            C<T> w = tw[TWOFF + (r - 1) * NS + kk];
             if (INV) w.y = -w.y;
             x = cmul(x, w);
           }
@@ -241,7 +307,7 @@ __device__ __forceinline__ void run_stages(C<T> *buf, const C<T> *tw) {
   constexpr RPlan P = make_rplan(N);
   if constexpr (S < P.n) {
     constexpr int R = P.r[S];
-    tstage<T, N, R, NS, INV, G, NT>(buf, tw);
+    tstage<T, N, R, NS, INV, G, NT, tw_off<N, false, S>()>(buf, tw);
     run_stages<T, N, INV, G, NT, S + 1, NS * R>(buf, tw);
   }
 }
@@ -249,6 +315,86 @@ __device__ __forceinline__ void run_stages(C<T> *buf, const C<T> *tw) {
 template <typename T, int N, bool INV, class G, int NT>
 __device__ __forceinline__ void fft_lines_t(C<T> *buf, const C<T> *tw) {
   run_stages<T, N, INV, G, NT, 0, 1>(buf, tw);
+}
+
+// ------------------------------------------- stages with explicit data paths
+//
+// The steady-state passes fuse the first and last radix stages with global
+// memory (inputs loaded straight into registers, outputs stored straight from
+// registers) and fuse an inverse transform's last stage with the next forward
+// transform's first stage (same radix, same thread map) around a pointwise
+// multiply, skipping LDS round trips.  A transform run with the reversed radix
+// plan consumes the natural-order output of the forward plan's last stage.
+
+template <class G, int N, int R, int NT> struct SG {
+  static constexpr int NR = N / R;
+  static constexpr int total = G::nlines * NR;
+  static constexpr int CAPQ = (total + NT - 1) / NT;
+  static __device__ __forceinline__ bool active(int q) { return total % NT == 0 || (int)threadIdx.x + q * NT < total; }
+  static __device__ __forceinline__ void jb(int q, int &j, int &b) {
+    const int f = (int)threadIdx.x + q * NT;
+    if constexpr (G::linefast) { b = f % G::nlines; j = f / G::nlines; }
+    else { j = f % NR; b = f / NR; }
+  }
+};
+
+// inputs x[b][j + r N/R] from src(b, n), twiddles of a stage with NS, radix-R DFT
+template <typename T, int N, int R, int NS, bool INV, class G, int NT, int TWOFF, int CQ, class Src>
+__device__ __forceinline__ void st_read(C<T> (&v)[CQ][R], const C<T> *tw, Src src) {
+  using S = SG<G, N, R, NT>;
+#pragma unroll
+  for (int q = 0; q < S::CAPQ; ++q) {
+    if (S::active(q)) {
+      int j, b;
+      S::jb(q, j, b);
+      const int kk = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C<T> x = src(b, j + r * S::NR);
+        if constexpr (NS > 1) {
+          if (r > 0) {
+            C<T> w = tw[TWOFF + (r - 1) * NS + kk];
+            if (INV) w.y = -w.y;
+            x = cmul(x, w);
+          }
+        }
+        v[q][r] = x;
+      }
+      Dft<R, INV, C<T>>::run(v[q]);
+    }
+  }
+}
+
+// outputs y[b][(j - j mod NS) R + j mod NS + r NS] to dst(b, n, value)
+template <typename T, int N, int R, int NS, class G, int NT, int CQ, class Dst>
+__device__ __forceinline__ void st_write(C<T> (&v)[CQ][R], Dst dst) {
+  using S = SG<G, N, R, NT>;
+#pragma unroll
+  for (int q = 0; q < S::CAPQ; ++q) {
+    if (S::active(q)) {
+      int j, b;
+      S::jb(q, j, b);
+      const int kk = j % NS;
+      const int base = (j - kk) * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst(b, base + r * NS, v[q][r]);
+    }
+  }
+}
+
+// stages [S0, S1) of plan (N, REV), LDS -> LDS
+template <typename T, int N, bool REV, bool INV, class G, int NT, int S0, int S1>
+__device__ __forceinline__ void lds_stages(C<T> *buf, const C<T> *tw) {
+  if constexpr (S0 < S1) {
+    constexpr int R = plan_of<N, REV>().r[S0];
+    constexpr int NS = ns_before<N, REV, S0>();
+    C<T> v[SG<G, N, R, NT>::CAPQ][R];
+    st_read<T, N, R, NS, INV, G, NT, tw_off<N, REV, S0>()>(v, tw, [&](int b, int n) { return buf[G::at(b, n)]; });
+    __syncthreads();
+    st_write<T, N, R, NS, G, NT>(v, [&](int b, int n, C<T> x) { buf[G::at(b, n)] = x; });
+    __syncthreads();
+    lds_stages<T, N, REV, INV, G, NT, S0 + 1, S1>(buf, tw);
+  }
 }
 
 }  // namespace qf

@@ -23,7 +23,7 @@ template <int N> __host__ __device__ constexpr int plane_threads() {
   return t < 64 ? 64 : (t > 1024 ? 1024 : t);
 }
 template <typename T, int N> __host__ __device__ constexpr size_t plane_lds_t() {
-  return (size_t)(N * padded_len(N) + N) * sizeof(C<T>);
+  return (size_t)(N * padded_len(N) + tw_total<N>()) * sizeof(C<T>);
 }
 template <typename T, int N> __host__ __device__ constexpr bool plane_fits() {
   return plane_lds_t<T, N>() <= 160 * 1024 && N * N <= 16 * 1024;
@@ -33,11 +33,11 @@ template <int N> __host__ __device__ constexpr int row_block_t() {
   return rb < 1 ? 1 : rb;
 }
 template <typename T, int N> __host__ __device__ constexpr size_t row_lds_t() {
-  return (size_t)(row_block_t<N>() * padded_len(N) + N) * sizeof(C<T>);
+  return (size_t)(row_block_t<N>() * padded_len(N) + tw_total<N>()) * sizeof(C<T>);
 }
 template <typename T> __host__ __device__ constexpr int col_tile_t() { return sizeof(T) == 4 ? 16 : 8; }
 template <typename T, int N> __host__ __device__ constexpr size_t col_lds_t() {
-  return (size_t)(N * (col_tile_t<T>() + 1) + N) * sizeof(C<T>);
+  return (size_t)(N * (col_tile_t<T>() + 1) + tw_total<N>()) * sizeof(C<T>);
 }
 
 // psi * f where f is real (T) or complex (C<T>) at site `off`.
@@ -62,11 +62,61 @@ __device__ __forceinline__ T kin_factor_t(const PassDesc &d, int i1, int i2, int
 
 template <typename T, int N, int NT>
 __device__ __forceinline__ void load_tw(C<T> *tw, const PassDesc &d) {
-  const C<T> *src = (const C<T> *)d.tw;
-  for (int i = threadIdx.x; i < N; i += NT) tw[i] = src[i];
+  fill_twiddles<T, N, NT>(tw, (const C<T> *)d.tw);
 }
 
 // ------------------------------------------------------------- plane pass
+
+// Steady-state plane pass (inverse x2,x3 -> x h^2 -> forward x3,x2) with the
+// first stage read from HBM, the last stage written to HBM, and the inverse-x3
+// last stage, the potential factor and the forward-x3 first stage fused in
+// registers.  The inverse uses the radix plan, the forward its reverse.
+template <typename T, int N, int NT, int P>
+__device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, const PassDesc &d, size_t voff) {
+  using Rows = RowsGeo<N, P>;
+  using Cols = ColsGeo<N, P>;
+  constexpr RPlan PL = plan_of<N, false>();
+  constexpr int M = PL.n - 1;
+  {
+    constexpr int R = PL.r[0];
+    C<T> v[SG<Cols, N, R, NT>::CAPQ][R];
+    st_read<T, N, R, 1, true, Cols, NT, 0>(v, tw, [&](int b, int n) { return g[n * N + b]; });
+    st_write<T, N, R, 1, Cols, NT>(v, [&](int b, int n, C<T> x) { pl[Cols::at(b, n)] = x; });
+    __syncthreads();
+  }
+  lds_stages<T, N, false, true, Cols, NT, 1, PL.n>(pl, tw);
+  lds_stages<T, N, false, true, Rows, NT, 0, M>(pl, tw);
+  {
+    constexpr int R = PL.r[M];
+    constexpr int NSL = ns_before<N, false, M>();
+    using S = SG<Rows, N, R, NT>;
+    C<T> v[S::CAPQ][R];
+    st_read<T, N, R, NSL, true, Rows, NT, tw_off<N, false, M>()>(v, tw, [&](int b, int n) { return pl[Rows::at(b, n)]; });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < S::CAPQ; ++q) {
+      if (S::active(q)) {
+        int j, b;
+        S::jb(q, j, b);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          v[q][r] = vmul_t<T>(v[q][r], d.h2fac, d.vcomplex, voff + (size_t)b * N + j + r * S::NR);
+        Dft<R, false, C<T>>::run(v[q]);
+      }
+    }
+    st_write<T, N, R, 1, Rows, NT>(v, [&](int b, int n, C<T> x) { pl[Rows::at(b, n)] = x; });
+    __syncthreads();
+  }
+  lds_stages<T, N, true, false, Rows, NT, 1, PL.n>(pl, tw);
+  lds_stages<T, N, true, false, Cols, NT, 0, M>(pl, tw);
+  {
+    constexpr int R = plan_of<N, true>().r[M];
+    constexpr int NSL = ns_before<N, true, M>();
+    C<T> v[SG<Cols, N, R, NT>::CAPQ][R];
+    st_read<T, N, R, NSL, false, Cols, NT, tw_off<N, true, M>()>(v, tw, [&](int b, int n) { return pl[Cols::at(b, n)]; });
+    st_write<T, N, R, NSL, Cols, NT>(v, [&](int b, int n, C<T> x) { g[n * N + b] = x; });
+  }
+}
 
 // Tile = one x2-x3 plane (state s, i1).
 template <typename T, int N>
@@ -85,6 +135,13 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_plane_t(const LaunchList
   constexpr size_t N2 = (size_t)N * N;
   C<T> *g = (C<T> *)d.psi + ((size_t)s * N + i1) * N2;
   const size_t voff = (size_t)i1 * N2;
+  if constexpr (plan_of<N, false>().n >= 2) {
+    if (mode == (M_INV | M_MID | M_FWD)) {
+      __syncthreads();
+      plane_steady<T, N, NT, P>(pl, tw, g, d, voff);
+      return;
+    }
+  }
   for (int idx = threadIdx.x; idx < N * N; idx += NT) {
     const int r = idx / N, c = idx - r * N;
     C<T> v = g[idx];
@@ -178,6 +235,61 @@ template <int NL, int PC> struct TileGeo {
   static __device__ __forceinline__ int at(int b, int n) { return n * PC + b; }
 };
 
+// Steady-state column pass (forward -> x e^{-dt T}/N^3 -> inverse) with the
+// first stage read from HBM, the last written to HBM, and the forward last
+// stage, the kinetic factor and the inverse first stage fused in registers.
+template <typename T, int N, int NT, class Geo>
+__device__ __forceinline__ void col_steady(C<T> *buf, const C<T> *tw, C<T> *g, size_t S, const PassDesc &d, bool ax1,
+                                           int o, int c0, int nc) {
+  constexpr RPlan PL = plan_of<N, false>();
+  constexpr int M = PL.n - 1;
+  constexpr int TC = Geo::nlines;
+  const C<T> zero = mkc<T>(0, 0);
+  {
+    constexpr int R = PL.r[0];
+    C<T> v[SG<Geo, N, R, NT>::CAPQ][R];
+    st_read<T, N, R, 1, false, Geo, NT, 0>(
+        v, tw, [&](int b, int n) { return (N % TC == 0 || b < nc) ? g[(size_t)n * S + b] : zero; });
+    st_write<T, N, R, 1, Geo, NT>(v, [&](int b, int n, C<T> x) { buf[Geo::at(b, n)] = x; });
+    __syncthreads();
+  }
+  lds_stages<T, N, false, false, Geo, NT, 1, M>(buf, tw);
+  {
+    constexpr int R = PL.r[M];
+    constexpr int NSL = ns_before<N, false, M>();
+    using SS = SG<Geo, N, R, NT>;
+    C<T> v[SS::CAPQ][R];
+    st_read<T, N, R, NSL, false, Geo, NT, tw_off<N, false, M>()>(v, tw, [&](int b, int n) { return buf[Geo::at(b, n)]; });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SS::CAPQ; ++q) {
+      if (SS::active(q)) {
+        int j, b;
+        SS::jb(q, j, b);
+        const int i3 = (N % TC == 0 || b < nc) ? c0 + b : c0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int n = j + r * SS::NR;
+          v[q][r] = cscale(v[q][r], kin_factor_t<T>(d, ax1 ? n : o, ax1 ? o : n, i3));
+        }
+        Dft<R, true, C<T>>::run(v[q]);
+      }
+    }
+    st_write<T, N, R, 1, Geo, NT>(v, [&](int b, int n, C<T> x) { buf[Geo::at(b, n)] = x; });
+    __syncthreads();
+  }
+  lds_stages<T, N, true, true, Geo, NT, 1, M>(buf, tw);
+  {
+    constexpr int R = plan_of<N, true>().r[M];
+    constexpr int NSL = ns_before<N, true, M>();
+    C<T> v[SG<Geo, N, R, NT>::CAPQ][R];
+    st_read<T, N, R, NSL, true, Geo, NT, tw_off<N, true, M>()>(v, tw, [&](int b, int n) { return buf[Geo::at(b, n)]; });
+    st_write<T, N, R, NSL, Geo, NT>(v, [&](int b, int n, C<T> x) {
+      if (N % TC == 0 || b < nc) g[(size_t)n * S + b] = x;
+    });
+  }
+}
+
 // Tile = TC contiguous x3 columns at one position of the other transverse
 // axis; all N elements along the transform axis (x1 if M_AXIS1, else x2).
 template <typename T, int N>
@@ -203,6 +315,14 @@ __global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
   C<T> *tw = buf + N * PC;
   load_tw<T, N, NT>(tw, d);
   C<T> *g = (C<T> *)d.psi + (size_t)s * N * N * N + (size_t)o * OS + c0;
+  using Geo = TileGeo<TC, PC>;
+  if constexpr (plan_of<N, false>().n >= 2) {
+    if ((mode & (M_FWD | M_KIN | M_INV | M_SCALE)) == (M_FWD | M_KIN | M_INV)) {
+      const int nc = (N - c0) < TC ? (N - c0) : TC;
+      col_steady<T, N, NT, Geo>(buf, tw, g, S, d, ax1, o, c0, nc);
+      return;
+    }
+  }
   for (int idx = threadIdx.x; idx < N * TC; idx += NT) {
     const int n = idx / TC, c = idx - n * TC;
     C<T> v = mkc<T>(0, 0);
@@ -210,7 +330,6 @@ __global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
     buf[n * PC + c] = v;
   }
   __syncthreads();
-  using Geo = TileGeo<TC, PC>;
   if (mode & M_FWD) fft_lines_t<T, N, false, Geo, NT>(buf, tw);
   if (mode & M_KIN) {
     for (int idx = threadIdx.x; idx < N * TC; idx += NT) {

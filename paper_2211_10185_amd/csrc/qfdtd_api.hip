@@ -35,6 +35,7 @@ void launch_dt_tables(bool dbl, const double *v64, int vcomplex, int N, double d
 void launch_from64_slot(bool dbl, void *dst, const double2 *src, size_t n, hipStream_t st);
 void launch_to64_slot(bool dbl, double2 *dst, const void *src, size_t n, hipStream_t st);
 int ew_tiles_host(long long n);
+int stencil_tiles_host(int N, int k);
 void launch_stencil(const LaunchList &L, int total, bool dbl, hipStream_t st);
 void launch_parity(const LaunchList &L, int total, bool dbl, hipStream_t st);
 void launch_to64(const LaunchList &L, int total, bool dbl, hipStream_t st);
@@ -134,8 +135,12 @@ struct qfdtd_ctx {
   void *psi = nullptr, *alt = nullptr, *vtab = nullptr, *hfac = nullptr, *h2fac = nullptr, *ktab = nullptr, *tw = nullptr;
   double2 *tw64 = nullptr, *scratch64 = nullptr;
   double *ksym64 = nullptr, *v64 = nullptr, *partials = nullptr, *coef = nullptr, *energy = nullptr, *trace = nullptr;
-  PassDesc *d_desc = nullptr;   // [0] main (state precision), [1] FP64 measurement copy
-  PassDesc hd[2];
+  PassDesc *d_desc = nullptr;   // [0] main, [1] FP64 measurement copy, [2], [3] state groups
+  PassDesc hd[4];
+  int ngroups = 1;              // 2: states split into two groups pipelined on two streams
+  int gk[2] = {0, 0};           // states per group
+  hipStream_t gst[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int nblk_red = 1;
   double cur_dt = -1.0;
   bool fresh = true;
@@ -199,7 +204,7 @@ qfdtd_status fail(qfdtd_ctx *c, qfdtd_status s, const std::string &msg) {
 
 // ------------------------------------------------------------- timing
 
-int tbegin(qfdtd_ctx *c, int cls, double bytes) {
+int tbegin(qfdtd_ctx *c, int cls, double bytes, hipStream_t st) {
   Timer &t = c->timer;
   if (t.every <= 0) return -1;
   if ((t.seen[cls]++ % t.every) != 0) return -1;
@@ -213,13 +218,13 @@ int tbegin(qfdtd_ctx *c, int cls, double bytes) {
   Timer::Rec &r = t.pool[t.used];
   r.cls = cls;
   r.bytes = bytes;
-  (void)hipEventRecord(r.a, c->st);
+  (void)hipEventRecord(r.a, st);
   return (int)t.used++;
 }
 
-void tend(qfdtd_ctx *c, int idx) {
+void tend(qfdtd_ctx *c, int idx, hipStream_t st) {
   if (idx < 0) return;
-  (void)hipEventRecord(c->timer.pool[idx].b, c->st);
+  (void)hipEventRecord(c->timer.pool[idx].b, st);
 }
 
 void tcollect(qfdtd_ctx *c) {
@@ -250,9 +255,11 @@ enum Fam { F_PLANE, F_ROW, F_COL, F_STENCIL, F_PARITY, F_TO64, F_GRAM, F_APPLY, 
 // algorithmic bytes moved by one member's share of a launch (for timing)
 double entry_bytes(const Entry &e, Fam f) {
   const qfdtd_ctx *c = e.c;
-  const double n = (double)c->k * c->n3();
-  const double s = e.which ? 16.0 : (double)c->csz();
-  const double fsz = (c->vcomplex ? 2.0 : 1.0) * (e.which ? 8.0 : (double)c->rsz());
+  const bool meas = e.which == 1;
+  const int k = e.which >= 2 ? c->gk[e.which - 2] : c->k;
+  const double n = (double)k * c->n3();
+  const double s = meas ? 16.0 : (double)c->csz();
+  const double fsz = (c->vcomplex ? 2.0 : 1.0) * (meas ? 8.0 : (double)c->rsz());
   switch (f) {
     case F_PLANE:
     case F_ROW: return n * (2 * s + ((e.mode & (M_PRE | M_MID | M_POST)) ? fsz : 0.0));
@@ -262,10 +269,10 @@ double entry_bytes(const Entry &e, Fam f) {
   }
 }
 
-qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS = 0);
+qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS = 0, hipStream_t sto = nullptr);
 
 // transform passes are instantiated per lattice size: one launch per distinct N
-qfdtd_status run_fft_family(Fam f, std::vector<Entry> &es, bool dbl) {
+qfdtd_status run_fft_family(Fam f, std::vector<Entry> &es, bool dbl, hipStream_t sto) {
   std::vector<int> sizes;
   for (auto &e : es)
     if (std::find(sizes.begin(), sizes.end(), e.c->N) == sizes.end()) sizes.push_back(e.c->N);
@@ -273,16 +280,16 @@ qfdtd_status run_fft_family(Fam f, std::vector<Entry> &es, bool dbl) {
     std::vector<Entry> sub;
     for (auto &e : es)
       if (e.c->N == N) sub.push_back(e);
-    QF_TRY(run_family(f, sub, dbl, -1));
+    QF_TRY(run_family(f, sub, dbl, -1, sto));
   }
   return QFDTD_OK;
 }
 
-qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS) {
+qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStream_t sto) {
   if (es.empty()) return QFDTD_OK;
-  if ((f == F_PLANE || f == F_ROW || f == F_COL) && KS != -1) return run_fft_family(f, es, dbl);
+  if ((f == F_PLANE || f == F_ROW || f == F_COL) && KS != -1) return run_fft_family(f, es, dbl, sto);
   qfdtd_ctx *c0 = es[0].c;
-  hipStream_t st = c0->st;
+  hipStream_t st = sto ? sto : c0->st;
   for (size_t base = 0; base < es.size(); base += MAX_LAUNCH) {
     LaunchList L;
     std::memset(&L, 0, sizeof(L));
@@ -312,7 +319,7 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS) {
     else if (f == F_ROW) cls = TC_ROW;
     else if (f == F_COL) cls = TC_COL;
     else if (f == F_STENCIL) cls = TC_STENCIL;
-    const int tix = cls >= 0 ? tbegin(c0, cls, bytes) : -1;
+    const int tix = cls >= 0 ? tbegin(c0, cls, bytes, st) : -1;
     const FftKernels &K = g_fft[es[base].c->N];
     void *kargs[] = {(void *)&L};
     switch (f) {
@@ -331,7 +338,7 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS) {
       case F_GFIN: launch_gram_finalize(L, st); break;
       case F_EFIN: launch_energy_finalize(L, st); break;
     }
-    tend(c0, tix);
+    tend(c0, tix, st);
     QF_LAUNCHED(c0);
   }
   return QFDTD_OK;
@@ -421,8 +428,35 @@ qfdtd_status energies(std::vector<qfdtd_ctx *> &ms, bool with_trace) {
 
 // ------------------------------------------------------------- one chunk
 
+// One FFT member with its states split into two groups, each group's pass
+// chain on its own stream: a group's plane pass (transform arithmetic bound)
+// overlaps the other group's column pass (memory bound).  Forked from and
+// joined to the context stream, so ordering with the caller is unchanged.
+qfdtd_status run_chunk_grouped(qfdtd_ctx *c, int n) {
+  const bool dbl = c->dbl;
+  QF_HIP(c, hipEventRecord(c->ev_fork, c->st));
+  for (int g = 0; g < 2; ++g) QF_HIP(c, hipStreamWaitEvent(c->gst[g], c->ev_fork, 0));
+  for (int g = 0; g < 2; ++g) {
+    const int which = 2 + g, kg = c->gk[g];
+    hipStream_t st = c->gst[g];
+    std::vector<Entry> pl{{c, which, M_PRE | M_FWD, plane_tiles(c->N, kg), 0}};
+    QF_TRY(run_family(F_PLANE, pl, dbl, 0, st));
+    for (int s = 0; s < n; ++s) {
+      std::vector<Entry> c1{{c, which, M_FWD | M_KIN | M_INV | M_AXIS1, col_tiles(c->N, kg, dbl), 0}};
+      const uint32_t rs = (s == n - 1) ? (M_INV | M_POST) : (M_INV | M_MID | M_FWD);
+      std::vector<Entry> p2{{c, which, rs, plane_tiles(c->N, kg), 0}};
+      QF_TRY(run_family(F_COL, c1, dbl, 0, st));
+      QF_TRY(run_family(F_PLANE, p2, dbl, 0, st));
+    }
+    QF_HIP(c, hipEventRecord(c->ev_join[g], st));
+  }
+  for (int g = 0; g < 2; ++g) QF_HIP(c, hipStreamWaitEvent(c->st, c->ev_join[g], 0));
+  return QFDTD_OK;
+}
+
 qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
   if (ms.empty()) return QFDTD_OK;
+  if (ms.size() == 1 && ms[0]->ngroups == 2 && n[0] > 0) return run_chunk_grouped(ms[0], n[0]);
   const bool dbl = ms[0]->dbl;
   int maxn = 0;
   for (int v : n) maxn = v > maxn ? v : maxn;
@@ -447,7 +481,7 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
       qfdtd_ctx *c = ms[j];
       if (s >= n[j]) continue;
       if (!c->fft()) {
-        sten.push_back({c, 0, c->cur ? (uint32_t)M_SWAP : 0u, ew_tiles_host((long long)c->k * c->n3()), 0});
+        sten.push_back({c, 0, c->cur ? (uint32_t)M_SWAP : 0u, stencil_tiles_host(c->N, c->k), 0});
         c->cur ^= 1;
         continue;
       }
@@ -481,7 +515,7 @@ qfdtd_status set_dt(qfdtd_ctx *c, double dt) {
   launch_dt_tables(c->dbl, c->v64, c->vcomplex ? 1 : 0, c->N, dt, c->vtab, c->hfac, c->h2fac, c->ktab, c->ksym64,
                    c->kin, c->st);
   QF_LAUNCHED(c);
-  for (int w = 0; w < 2; ++w) {
+  for (int w = 0; w < 4; ++w) {
     c->hd[w].dt = dt;
     c->hd[w].stencil_c = dt / (2.0 * c->m * c->a * c->a);
   }
@@ -652,6 +686,11 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   c->trace_cap = c->trace_on ? 4096 : 0;
 
   auto bail = [&](qfdtd_status s, const std::string &msg) {
+    for (int g = 0; g < 2; ++g) {
+      if (c->gst[g]) (void)hipStreamDestroy(c->gst[g]);
+      if (c->ev_join[g]) (void)hipEventDestroy(c->ev_join[g]);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     free_all(c);
     if (c->h_status) (void)hipHostFree(c->h_status);
     if (c->status_ev) (void)hipEventDestroy(c->status_ev);
@@ -751,6 +790,26 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     d.nblk_red = c->nblk_red;
     d.a = a; d.m = m; d.dt = 0.0; d.stencil_c = 0.0;
     d.inv_n3 = 1.0 / (double)n3;
+  }
+  // state groups for the two-stream schedule (plane schedule, k >= 2)
+  if (c->fft() && c->plane && c->k >= 2 && !(o.flags & QFDTD_F_SINGLE_STREAM)) {
+    c->ngroups = 2;
+    c->gk[0] = (c->k + 1) / 2;
+    c->gk[1] = c->k - c->gk[0];
+    for (int g = 0; g < 2; ++g) {
+      c->hd[2 + g] = c->hd[0];
+      c->hd[2 + g].psi = (char *)c->psi + (size_t)(g ? c->gk[0] : 0) * n3 * cs;
+      c->hd[2 + g].k = c->gk[g];
+    }
+    bool okg = hipStreamCreateWithFlags(&c->gst[0], hipStreamNonBlocking) == hipSuccess &&
+               hipStreamCreateWithFlags(&c->gst[1], hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&c->ev_join[0], hipEventDisableTiming) == hipSuccess &&
+               hipEventCreateWithFlags(&c->ev_join[1], hipEventDisableTiming) == hipSuccess;
+    if (!okg) return bail(QFDTD_E_DEVICE, "stream creation failed");
+  } else {
+    c->hd[2] = c->hd[0];
+    c->hd[3] = c->hd[0];
   }
   if (upload_desc(c) != QFDTD_OK || hipMemsetAsync(c->energy, 0, (2 * MAX_STATES + 8) * 8, c->st) != hipSuccess ||
       hipStreamSynchronize(c->st) != hipSuccess)
@@ -972,6 +1031,11 @@ void qfdtd_destroy(qfdtd_ctx *c) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
+  for (int g = 0; g < 2; ++g) {
+    if (c->gst[g]) { (void)hipStreamSynchronize(c->gst[g]); (void)hipStreamDestroy(c->gst[g]); }
+    if (c->ev_join[g]) (void)hipEventDestroy(c->ev_join[g]);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   free_all(c);
   if (c->h_status) (void)hipHostFree(c->h_status);
   if (c->status_ev) (void)hipEventDestroy(c->status_ev);

@@ -77,7 +77,8 @@ class Solver:
     def __init__(self, N: int, a: float, m: float, kinetic: int, vkind: int,
                  vparams: Sequence[float] = (), knots=None, grid=None, precision: int = C64,
                  n_states: int = 3, sectors: Optional[Sequence[int]] = None,
-                 measure_every: int = 50, trace: bool = False, torch_alloc: bool = True):
+                 measure_every: int = 50, trace: bool = False, torch_alloc: bool = True,
+                 single_stream: bool = False):
         torch = _torch()
         self.N, self.a, self.m, self.kinetic = int(N), float(a), float(m), int(kinetic)
         self.precision, self.k = int(precision), int(n_states)
@@ -93,6 +94,7 @@ class Solver:
             opt.sectors = ct.cast(sec, ct.POINTER(ct.c_int32))
         opt.measure_every = int(measure_every)
         opt.trace_energies = 1 if trace else 0
+        opt.flags = L.F_SINGLE_STREAM if single_stream else 0
         opt.hip_stream = ct.c_void_p(self.stream.cuda_stream)
         if self._alloc is not None:
             opt.dev_alloc = self._alloc.alloc
