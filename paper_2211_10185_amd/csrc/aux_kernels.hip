@@ -630,9 +630,8 @@ void launch_to64_slot(bool dbl, double2 *dst, const void *src, size_t n, hipStre
 int ew_tiles_host(long long n) { return ew_tiles(n); }
 int stencil_tiles_host(int N, int k) { return stencil_tiles(N, k); }
 
-void launch_stencil(const LaunchList &L, int total, bool dbl, hipStream_t st) {
-  if (dbl) hipLaunchKernelGGL(k_stencil<double>, dim3(total), dim3(RED_THREADS), 0, st, L);
-  else hipLaunchKernelGGL(k_stencil<float>, dim3(total), dim3(RED_THREADS), 0, st, L);
+const void *stencil_kernel(bool dbl) {
+  return dbl ? (const void *)k_stencil<double> : (const void *)k_stencil<float>;
 }
 void launch_parity(const LaunchList &L, int total, bool dbl, hipStream_t st) {
   if (dbl) hipLaunchKernelGGL(k_parity<double>, dim3(total), dim3(RED_THREADS), 0, st, L);

@@ -1,0 +1,146 @@
+"""Continuous-batching serving loop over the solver's C ABI.
+
+Requests (one lattice problem each, k = 1 state) arrive over time.  The loop
+keeps every admitted solve resident on the GPU and advances all of them
+together one chunk (K imaginary-time steps) at a time with
+``qfdtd_batch_evolve``; after each chunk it reads every solve's FP64 ground
+energy with ``qfdtd_batch_energies`` and retires the solves whose energy moved
+by less than ``tol`` since the previous chunk.  Requests that arrived in the
+meantime are admitted at the next chunk boundary while device memory (by the
+library's own footprint estimate) and slots allow, so their work overlaps with
+the solves already running.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+
+from . import solver as S
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    N: int
+    kinetic: int
+    energy: complex
+    steps: int
+    converged: bool
+    t_arrival: float
+    t_admit: float
+    t_done: float
+    psi: Optional[np.ndarray] = None
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+@dataclasses.dataclass
+class _Active:
+    req: object
+    solver: S.Solver
+    footprint: int
+    t_admit: float
+    prev: Optional[complex] = None
+    steps: int = 0
+
+
+def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int] = None,
+          max_slots: int = 64, tol: float = 1e-8, max_steps: int = 50000, chunk: Optional[int] = None,
+          keep_psi: bool = False, realtime: bool = True,
+          clock: Callable[[], float] = time.perf_counter) -> dict:
+    """Serve ``requests`` (objects with .rid, .arrival (s), .problem); return results and stats.
+
+    ``realtime``: admit a request only once the wall clock has passed its arrival
+    time; otherwise every request counts as arrived at t = 0 (a closed backlog).
+    """
+    import torch
+    if budget_bytes is None:
+        free, _total = torch.cuda.mem_get_info()
+        budget_bytes = int(0.8 * free)
+    pending = sorted(requests, key=lambda r: r.arrival)
+    active: List[_Active] = []
+    done: List[Result] = []
+    used = 0
+    peak_used = 0
+    peak_active = 0
+    chunks = 0
+    t0 = clock()
+
+    def now():
+        return clock() - t0
+
+    while pending or active:
+        t = now()
+        # admission: arrived requests, in arrival order, while slots and memory allow
+        while pending and (not realtime or pending[0].arrival <= t) and len(active) < max_slots:
+            p = pending[0].problem
+            fp = S.footprint(p.N, p.kinetic, precision, p.k)
+            if used + fp > budget_bytes and active:
+                break
+            req = pending.pop(0)
+            sv = S.Solver.from_problem(p, precision=precision)
+            sv.set_states(p.init_states())
+            active.append(_Active(req, sv, fp, now()))
+            used += fp
+        peak_used = max(peak_used, used)
+        peak_active = max(peak_active, len(active))
+        if not active:
+            # idle until the next arrival
+            wait = pending[0].arrival - now()
+            if wait > 0:
+                time.sleep(min(wait, 0.01))
+            continue
+        K = chunk or active[0].req.problem.measure_every
+        dts = [a.req.problem.dt for a in active]
+        S.batch_evolve([a.solver for a in active], K, dts)
+        E = S.batch_energies([a.solver for a in active])[:, 0]
+        chunks += 1
+        keep = []
+        for a, e in zip(active, E):
+            a.steps += K
+            conv = a.prev is not None and abs(e - a.prev) < tol
+            if conv or a.steps >= max_steps:
+                psi = a.solver.states(1)[1][0] if keep_psi else None
+                done.append(Result(a.req.rid, a.req.problem.N, a.req.problem.kinetic, complex(e), a.steps, conv,
+                                   a.req.arrival if realtime else 0.0, a.t_admit, now(), psi))
+                a.solver.close()
+                used -= a.footprint
+            else:
+                a.prev = complex(e)
+                keep.append(a)
+        active = keep
+    makespan = now()
+    lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+    return {"results": sorted(done, key=lambda r: r.rid), "makespan_s": makespan,
+            "solves_per_s": len(done) / makespan if makespan > 0 else 0.0,
+            "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+            "peak_active": peak_active, "peak_footprint_bytes": peak_used, "budget_bytes": budget_bytes,
+            "chunks": chunks}
+
+
+def solve_alone(req, precision: int = S.C64, tol: float = 1e-8, max_steps: int = 50000,
+                chunk: Optional[int] = None, keep_psi: bool = False) -> Result:
+    """The plain single-solve path: one request on its own, same stopping rule."""
+    p = req.problem
+    t0 = time.perf_counter()
+    sv = S.Solver.from_problem(p, precision=precision)
+    sv.set_states(p.init_states())
+    K = chunk or p.measure_every
+    prev, steps, conv, e = None, 0, False, None
+    while steps < max_steps:
+        sv.evolve(K, p.dt)
+        steps += K
+        e = complex(sv.energies()[0])
+        if prev is not None and abs(e - prev) < tol:
+            conv = True
+            break
+        prev = e
+    psi = sv.states(1)[1][0] if keep_psi else None
+    sv.close()
+    t1 = time.perf_counter()
+    return Result(req.rid, p.N, p.kinetic, e, steps, conv, 0.0, 0.0, t1 - t0, psi)

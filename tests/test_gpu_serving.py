@@ -1,0 +1,94 @@
+"""Serving loop and batched uneven lattices on the GPU."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from compare import energy_errors, phase_aligned_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def small_trace(n=6, seed=205, sizes=(32, 36, 40, 48, 50, 54), gap=0.002):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    for j in range(n):
+        N = int(sizes[j % len(sizes)])
+        kind = [S.K_NR_P2, S.K_NR_SIN2, S.K_REL][j % 3]
+        p = S.Problem(N=N, a=8.0 / N, m=1.0, kinetic=kind, vkind=S.V_RADIAL_SPLINE,
+                      knots=S.spline_knots(8.0, seed * 100 + j), k=1, precision=S.PREC_C64, dt=0.01,
+                      steps=50000, measure_every=50, seed=seed * 1000 + j)
+        reqs.append(S.Request(rid=j, arrival=j * gap + float(rng.uniform(0, gap)), problem=p))
+    return reqs
+
+
+def test_serving_result_is_the_same_alone_and_in_the_mix():
+    from paper_2211_10185_amd.serving import serve, solve_alone
+    reqs = small_trace()
+    out = serve(reqs, keep_psi=True, tol=1e-8, max_steps=4000)
+    assert len(out["results"]) == len(reqs)
+    assert out["peak_active"] >= 2          # requests really overlapped on the device
+    for r, q in zip(out["results"], reqs):
+        alone = solve_alone(q, tol=1e-8, max_steps=4000, keep_psi=True)
+        assert r.steps == alone.steps
+        assert r.energy == alone.energy       # identical bits: deterministic kernels and reductions
+        assert np.array_equal(r.psi, alone.psi)
+        assert r.converged
+
+
+def test_admission_respects_footprint_budget():
+    from paper_2211_10185_amd.serving import serve
+    from paper_2211_10185_amd.solver import footprint
+    reqs = small_trace(n=5, sizes=(48,), gap=0.0)
+    fp = footprint(48, S.K_NR_P2, 0, 1)
+    out = serve(reqs, budget_bytes=2 * fp + fp // 2, tol=1e-7, max_steps=2000)
+    assert out["peak_footprint_bytes"] <= 2 * fp + fp // 2
+    assert out["peak_active"] == 2
+    assert len(out["results"]) == 5
+    out1 = serve(reqs, max_slots=1, tol=1e-7, max_steps=2000)
+    assert out1["peak_active"] == 1
+    for a, b in zip(out["results"], out1["results"]):
+        assert a.energy == b.energy
+
+
+def test_serving_fp32_vs_fp64_and_oracle():
+    from paper_2211_10185_amd.serving import serve
+    reqs = small_trace(n=3)
+    o32 = serve(reqs, precision=0, tol=1e-8, max_steps=3000, realtime=False)
+    o64 = serve(reqs, precision=1, tol=1e-8, max_steps=3000, realtime=False)
+    for a, b, q in zip(o32["results"], o64["results"], reqs):
+        assert abs(a.energy - b.energy) <= 1e-5 * max(abs(b.energy), 1e-2)
+        # the FP64 path against the oracle at the same number of steps
+        ref = O.solve(q.problem, steps=b.steps)
+        assert np.max(energy_errors([b.energy], ref["energies"][:1])) < 1e-10
+
+
+def test_batch_of_uneven_cornell_lattices_matches_oracle_and_alone():
+    from paper_2211_10185_amd.solver import Solver, batch_evolve
+    members = S.config4(n=64)
+    # sample: one member of each size, a short run
+    pick, seen = [], set()
+    for p in members:
+        if p.N not in seen:
+            seen.add(p.N)
+            pick.append(p)
+    for p in pick:
+        p.measure_every = 10
+    ss = [Solver.from_problem(p) for p in pick]
+    for s, p in zip(ss, pick):
+        s.set_states(p.init_states())
+    batch_evolve(ss, 25, [p.dt for p in pick])
+    for s, p in zip(ss, pick):
+        E, psi = s.states()
+        s.close()
+        alone = Solver.from_problem(p)
+        alone.set_states(p.init_states())
+        alone.evolve(25, p.dt)
+        Ea, psia = alone.states()
+        alone.close()
+        assert np.array_equal(E, Ea) and np.array_equal(psi, psia)
+        if p.N <= 80:   # oracle cost bound
+            ref = O.solve(p, steps=25)
+            assert np.max(energy_errors(E, ref["energies"])) < 1e-5
+            for i in range(p.k):
+                assert phase_aligned_l2(psi[i], ref["states"][i]) < 1e-4
