@@ -118,6 +118,8 @@ typedef struct {
 /* qfdtd_options.flags */
 #define QFDTD_F_SINGLE_STREAM 1u  /* do not split the states of an FFT solve into two
                                      groups evolved on two internal streams */
+#define QFDTD_F_ROWCOL 2u         /* FFT kinds: use the row + three column pass schedule even
+                                     where an x2-x3 plane fits in LDS (schedule autotuning) */
 
 typedef struct qfdtd_ctx qfdtd_ctx;
 

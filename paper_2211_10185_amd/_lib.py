@@ -39,6 +39,7 @@ class Options(ct.Structure):
                 ("flags", ct.c_uint32)]
 
 F_SINGLE_STREAM = 1
+F_ROWCOL = 2
 
 
 class QfdtdError(RuntimeError):

@@ -1,0 +1,138 @@
+"""Pass-schedule autotuner for the FFT kinetic terms.
+
+For a lattice size N, a state precision and a state count, the solver can run a
+step as
+  * the plane schedule (x2-x3 plane pass + x1 column pass: 2 passes per step),
+    available where an N^2 plane fits in LDS, or
+  * the row/column schedule (x3 row pass + three column passes: 4 passes),
+and, with k >= 2 states, either carry all states through one stream or split
+them into two groups pipelined on two streams.  ``tune`` times every candidate
+on the device with the solver's own kernels and records the fastest in a JSON
+cache; ``schedule_for`` is what ``Solver`` consults at creation.
+
+Cache: ``$QFDTD_TUNING`` if set, else ``tuning.json`` next to this file.
+Entry key: "N/precision/states" with states clipped to {1, 2+}.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict, Iterable, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PLANE_LIMIT = {0: 128, 1: 96}      # largest N whose plane fits LDS (complex64 / complex128)
+_cache: Optional[Dict[str, dict]] = None
+
+
+def cache_path() -> str:
+    return os.environ.get("QFDTD_TUNING", os.path.join(HERE, "tuning.json"))
+
+
+def _load() -> Dict[str, dict]:
+    global _cache
+    if _cache is None:
+        try:
+            with open(cache_path()) as f:
+                _cache = json.load(f).get("entries", {})
+        except (OSError, ValueError):
+            _cache = {}
+    return _cache
+
+
+def key(N: int, precision: int, k: int) -> str:
+    return "%d/%d/%d" % (N, precision, 1 if k <= 1 else 2)
+
+
+def default_schedule(N: int, kinetic: int, precision: int, k: int) -> dict:
+    # without a measurement: two streams pay off only once a group's passes fill the GPU
+    return {"rowcol": False, "single_stream": k < 2 or N < 96}
+
+
+def schedule_for(N: int, kinetic: int, precision: int, k: int) -> dict:
+    """Tuned schedule if the cache has one for (N, precision, k), else the default."""
+    if kinetic == 0:
+        return {"rowcol": False, "single_stream": True}
+    e = _load().get(key(N, precision, k))
+    if e is None:
+        return default_schedule(N, kinetic, precision, k)
+    return {"rowcol": bool(e["rowcol"]), "single_stream": bool(e["single_stream"])}
+
+
+def candidates(N: int, precision: int, k: int):
+    out = []
+    plane_ok = N <= PLANE_LIMIT[precision]
+    for rowcol in ([False, True] if plane_ok else [True]):
+        for single in ([True, False] if (k >= 2 and not rowcol) else [True]):
+            out.append({"rowcol": rowcol, "single_stream": single})
+    return out
+
+
+def time_schedule(N: int, precision: int, k: int, sched: dict, steps: int = 200, kinetic: int = 2) -> float:
+    """Microseconds per imaginary-time step of a harmonic problem under `sched`."""
+    import torch
+    import synthetic as S
+    from .solver import Solver
+    a = 8.0 / N
+    s = Solver(N, a, 1.0, kinetic, S.V_HARMONIC, (1.0,), precision=precision, n_states=k,
+               single_stream=sched["single_stream"], rowcol=sched["rowcol"])
+    s.set_states(S.initial_states(N, k, 7))
+    dt = a * a / 8
+    s.evolve(50, dt)
+    s.energies()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.evolve(steps, dt)
+    s.energies()
+    torch.cuda.synchronize()
+    us = 1e6 * (time.perf_counter() - t0) / steps
+    s.close()
+    return us
+
+
+def tune(sizes: Iterable[int], precisions: Iterable[int] = (0,), states: Iterable[int] = (1, 3),
+         steps: int = 200, path: Optional[str] = None, verbose: bool = True) -> Dict[str, dict]:
+    """Time every candidate schedule and write the winners to the cache."""
+    global _cache
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            doc = json.load(f)
+    except (OSError, ValueError):
+        doc = {"entries": {}}
+    entries = doc.setdefault("entries", {})
+    for N in sizes:
+        for prec in precisions:
+            for k in states:
+                times = {}
+                for c in candidates(N, prec, k):
+                    name = ("rowcol" if c["rowcol"] else "plane") + ("/1stream" if c["single_stream"] else "/2streams")
+                    times[name] = time_schedule(N, prec, k, c, steps)
+                best = min(times, key=times.get)
+                entries[key(N, prec, k)] = {"rowcol": best.startswith("rowcol"),
+                                            "single_stream": best.endswith("1stream"),
+                                            "us_per_step": {n: round(v, 2) for n, v in times.items()}}
+                if verbose:
+                    print("tune N=%d prec=%d k=%d -> %s %s" % (N, prec, k, best, entries[key(N, prec, k)]["us_per_step"]),
+                          flush=True)
+    doc["device"] = _device_name()
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1, sort_keys=True)
+    _cache = None
+    return entries
+
+
+def _device_name() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_name(0)
+    except Exception:
+        return "unknown"
+
+
+if __name__ == "__main__":
+    import sys
+    import synthetic as S
+    out = sys.argv[1] if len(sys.argv) > 1 else None
+    sizes = [n for n in S.smooth_even_sizes(32, 256)]
+    tune(sizes, precisions=(0, 1), states=(1, 3), steps=100, path=out)

@@ -24,7 +24,9 @@ ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code (see the
 # target-feature pair below); the compiler then emits scalar FP32 VALU ops.
-FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+# -ffp-contract=off: no implicit mul+add fusion; the kernels spell out their
+# FMAs, so every instantiation of a pass computes bit-identical results.
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC]
 

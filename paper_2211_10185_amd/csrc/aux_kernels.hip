@@ -143,9 +143,10 @@ __device__ __forceinline__ C<T> fdtd_update(C<T> cur, C<T> acc, const void *__re
     return cadd(cmul(A, cur), cmul(B, cscale(acc, c)));
   } else {
     const T V = ((const T *)vtab)[off];
-    const T B = (T)1 / ((T)1 + hdt * V);
-    const T A = ((T)1 - hdt * V) * B;
-    return cadd(cscale(cur, A), cscale(acc, B * c));
+    const T B = (T)1 / fmaT(hdt, V, (T)1);
+    const T A = fmaT(-hdt, V, (T)1) * B;
+    const T Bc = B * c;
+    return mkc<T>(fmaT(A, cur.x, Bc * acc.x), fmaT(A, cur.y, Bc * acc.y));
   }
 }
 

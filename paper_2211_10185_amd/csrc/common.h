@@ -28,8 +28,18 @@ template <typename T> using C = typename CT<T>::type;
 template <typename T> __host__ __device__ __forceinline__ C<T> mkc(T x, T y) { C<T> r; r.x = x; r.y = y; return r; }
 template <typename V> __host__ __device__ __forceinline__ V cadd(V a, V b) { V r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
 template <typename V> __host__ __device__ __forceinline__ V csub(V a, V b) { V r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+// Fused multiply-add written out: device code is compiled with
+// -ffp-contract=off, so the rounding of every expression is fixed by the
+// source and identical in every kernel instantiation (a member advanced by a
+// single-size kernel or by a multi-size kernel gets the same bits).
+__host__ __device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+
 template <typename V> __host__ __device__ __forceinline__ V cmul(V a, V b) {
-  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+  V r;
+  r.x = fmaT(a.x, b.x, -(a.y * b.y));
+  r.y = fmaT(a.x, b.y, a.y * b.x);
+  return r;
 }
 template <typename V, typename S> __host__ __device__ __forceinline__ V cscale(V a, S s) { V r; r.x = a.x * s; r.y = a.y * s; return r; }
 // multiply by -i (forward) or +i (inverse)
@@ -118,6 +128,19 @@ struct FftKernels {
   size_t plane_lds[2], row_lds[2], col_lds[2];
   int plane_nt;
 };
+
+// Multi-size transform-pass kernels of one size group (see fft_inst.hip).
+struct GroupKernels {
+  const void *plane[2];
+  const void *row[2];
+  const void *col[2];
+  int plane_nt[2];
+};
+
+// Size group of a lattice size (groups of fft_inst.hip).
+__host__ __device__ inline int size_group(int N) {
+  return N <= 32 ? 0 : (N <= 80 ? 1 : (N <= 128 ? 2 : (N <= 180 ? 3 : 4)));
+}
 
 // Threads per block of each kernel family.
 constexpr int LINE_THREADS = 256;

@@ -87,8 +87,8 @@ __device__ __forceinline__ V rot16(V a) {
     const T c = (T)cs[m];
     const T s = INV ? (T)sn[m] : (T)-sn[m];
     V r;
-    r.x = a.x * c - a.y * s;
-    r.y = a.x * s + a.y * c;
+    r.x = fmaT(a.x, c, -(a.y * s));
+    r.y = fmaT(a.x, s, a.y * c);
     return r;
   }
 }
@@ -139,7 +139,9 @@ template <bool INV, typename V> struct Dft<3, INV, V> {
     const T s = (T)0.86602540378443864676;
     V t = cadd(v[1], v[2]);
     V u = cscale(csub(v[1], v[2]), s);
-    V a = csub(v[0], cscale(t, (T)0.5));
+    V a;
+    a.x = fmaT((T)-0.5, t.x, v[0].x);
+    a.y = fmaT((T)-0.5, t.y, v[0].y);
     V iu = mul_mi<INV>(u);
     v[0] = cadd(v[0], t);
     v[1] = cadd(a, iu);
@@ -154,10 +156,17 @@ template <bool INV, typename V> struct Dft<5, INV, V> {
     const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;
     V t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
     V u1 = csub(v[1], v[4]), u2 = csub(v[2], v[3]);
-    V a1 = cadd(v[0], cadd(cscale(t1, c1), cscale(t2, c2)));
-    V a2 = cadd(v[0], cadd(cscale(t1, c2), cscale(t2, c1)));
-    V b1 = mul_mi<INV>(cadd(cscale(u1, s1), cscale(u2, s2)));
-    V b2 = mul_mi<INV>(csub(cscale(u1, s2), cscale(u2, s1)));
+    V a1, a2, p1, p2;
+    a1.x = fmaT(c2, t2.x, fmaT(c1, t1.x, v[0].x));
+    a1.y = fmaT(c2, t2.y, fmaT(c1, t1.y, v[0].y));
+    a2.x = fmaT(c1, t2.x, fmaT(c2, t1.x, v[0].x));
+    a2.y = fmaT(c1, t2.y, fmaT(c2, t1.y, v[0].y));
+    p1.x = fmaT(s2, u2.x, s1 * u1.x);
+    p1.y = fmaT(s2, u2.y, s1 * u1.y);
+    p2.x = fmaT(-s1, u2.x, s2 * u1.x);
+    p2.y = fmaT(-s1, u2.y, s2 * u1.y);
+    V b1 = mul_mi<INV>(p1);
+    V b2 = mul_mi<INV>(p2);
     v[0] = cadd(v[0], cadd(t1, t2));
     v[1] = cadd(a1, b1);
     v[4] = csub(a1, b1);

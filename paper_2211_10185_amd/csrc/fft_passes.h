@@ -118,16 +118,14 @@ __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, 
   }
 }
 
-// Tile = one x2-x3 plane (state s, i1).
-template <typename T, int N>
-__global__ void __launch_bounds__(plane_threads<N>()) k_plane_t(const LaunchList L) {
-  constexpr int NT = plane_threads<N>();
+// Tile = one x2-x3 plane (state s, i1).  NT = threads of the block (the
+// plane kernel of a single size uses plane_threads<N>(); a multi-size kernel
+// runs every size with its own, larger, block).
+template <typename T, int N, int NT>
+__device__ __forceinline__ void plane_body(const LaunchList &L, int e, int t, unsigned char *smem) {
   constexpr int P = padded_len(N);
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int e = find_entry(L, blockIdx.x);
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
-  const int t = blockIdx.x - L.tile_start[e];
   const int s = t / N, i1 = t - s * N;
   C<T> *pl = (C<T> *)smem;
   C<T> *tw = pl + N * P;
@@ -175,19 +173,22 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_plane_t(const LaunchList
   }
 }
 
+template <typename T, int N>
+__global__ void __launch_bounds__(plane_threads<N>()) k_plane_t(const LaunchList L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int e = find_entry(L, blockIdx.x);
+  plane_body<T, N, plane_threads<N>()>(L, e, blockIdx.x - L.tile_start[e], smem);
+}
+
 // --------------------------------------------------------------- row pass
 
 // Tile = RB consecutive x3 rows over all states (the last tile may be short).
-template <typename T, int N>
-__global__ void __launch_bounds__(LINE_THREADS) k_row_t(const LaunchList L) {
-  constexpr int NT = LINE_THREADS;
+template <typename T, int N, int NT>
+__device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsigned char *smem) {
   constexpr int P = padded_len(N);
   constexpr int RB = row_block_t<N>();
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int e = find_entry(L, blockIdx.x);
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
-  const int t = blockIdx.x - L.tile_start[e];
   const long long rows_total = (long long)d.k * N * N;
   const long long row0 = (long long)t * RB;
   const int nrows = (int)((rows_total - row0) < RB ? (rows_total - row0) : RB);
@@ -225,6 +226,13 @@ __global__ void __launch_bounds__(LINE_THREADS) k_row_t(const LaunchList L) {
     if (mode & M_POST) v = vmul_t<T>(v, d.hfac, d.vcomplex, (voff0 + idx) % N3);
     g[idx] = v;
   }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(LINE_THREADS) k_row_t(const LaunchList L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int e = find_entry(L, blockIdx.x);
+  row_body<T, N, LINE_THREADS>(L, e, blockIdx.x - L.tile_start[e], smem);
 }
 
 // ------------------------------------------------------------ column pass
@@ -292,17 +300,13 @@ __device__ __forceinline__ void col_steady(C<T> *buf, const C<T> *tw, C<T> *g, s
 
 // Tile = TC contiguous x3 columns at one position of the other transverse
 // axis; all N elements along the transform axis (x1 if M_AXIS1, else x2).
-template <typename T, int N>
-__global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
-  constexpr int NT = LINE_THREADS;
+template <typename T, int N, int NT>
+__device__ __forceinline__ void col_body(const LaunchList &L, int e, int t, unsigned char *smem) {
   constexpr int TC = col_tile_t<T>();
   constexpr int PC = TC + 1;
   constexpr int NCB = (N + TC - 1) / TC;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int e = find_entry(L, blockIdx.x);
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
-  const int t = blockIdx.x - L.tile_start[e];
   constexpr int per_state = N * NCB;
   const int s = t / per_state;
   const int rem = t - s * per_state;
@@ -347,6 +351,13 @@ __global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
     const int n = idx / TC, c = idx - n * TC;
     if (N % TC == 0 || c0 + c < N) g[(size_t)n * S + c] = cscale(buf[n * PC + c], post);
   }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int e = find_entry(L, blockIdx.x);
+  col_body<T, N, LINE_THREADS>(L, e, blockIdx.x - L.tile_start[e], smem);
 }
 
 // ------------------------------------------------------------ dispatch table

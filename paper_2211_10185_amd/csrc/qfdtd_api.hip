@@ -23,11 +23,11 @@
 #include <hip/hip_ext.h>
 
 namespace qf {
-void register_fft_group0(FftKernels *t);
-void register_fft_group1(FftKernels *t);
-void register_fft_group2(FftKernels *t);
-void register_fft_group3(FftKernels *t);
-void register_fft_group4(FftKernels *t);
+void register_fft_group0(FftKernels *t, GroupKernels *g);
+void register_fft_group1(FftKernels *t, GroupKernels *g);
+void register_fft_group2(FftKernels *t, GroupKernels *g);
+void register_fft_group3(FftKernels *t, GroupKernels *g);
+void register_fft_group4(FftKernels *t, GroupKernels *g);
 void launch_tables(bool dbl, void *tw, double2 *tw64, double *ksym64, int N, int kin, double a, double m, hipStream_t st);
 void launch_potential(double *v64, int vcomplex, int N, double a, int kind, const double *p, const double *knots, int nk,
                       const double2 *add, hipStream_t st);
@@ -85,16 +85,37 @@ int make_plan(int N, int32_t *radix) {
 }
 
 FftKernels g_fft[257];
+GroupKernels g_grp[5];
+size_t g_grp_lds[5][3][2];   // per group, kind (plane, row, col), precision: largest LDS of its sizes
 
 hipError_t fft_table_init() {
   static bool done = false;
   if (done) return hipSuccess;
   std::memset(g_fft, 0, sizeof(g_fft));
-  register_fft_group0(g_fft);
-  register_fft_group1(g_fft);
-  register_fft_group2(g_fft);
-  register_fft_group3(g_fft);
-  register_fft_group4(g_fft);
+  std::memset(g_grp, 0, sizeof(g_grp));
+  std::memset(g_grp_lds, 0, sizeof(g_grp_lds));
+  register_fft_group0(g_fft, &g_grp[0]);
+  register_fft_group1(g_fft, &g_grp[1]);
+  register_fft_group2(g_fft, &g_grp[2]);
+  register_fft_group3(g_fft, &g_grp[3]);
+  register_fft_group4(g_fft, &g_grp[4]);
+  for (int n = 8; n <= 256; ++n)
+    for (int w = 0; w < 2; ++w) {
+      const int gi = size_group(n);
+      if (g_fft[n].plane[w]) g_grp_lds[gi][0][w] = std::max(g_grp_lds[gi][0][w], g_fft[n].plane_lds[w]);
+      if (g_fft[n].row[w]) g_grp_lds[gi][1][w] = std::max(g_grp_lds[gi][1][w], g_fft[n].row_lds[w]);
+      if (g_fft[n].col[w]) g_grp_lds[gi][2][w] = std::max(g_grp_lds[gi][2][w], g_fft[n].col_lds[w]);
+    }
+  for (int gi = 0; gi < 5; ++gi)
+    for (int w = 0; w < 2; ++w) {
+      const void *fs[3] = {g_grp[gi].plane[w], g_grp[gi].row[w], g_grp[gi].col[w]};
+      for (int q = 0; q < 3; ++q)
+        if (fs[q]) {
+          hipError_t e = hipFuncSetAttribute(fs[q], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)g_grp_lds[gi][q][w]);
+          if (e != hipSuccess) return e;
+        }
+    }
   for (int n = 0; n <= 256; ++n)
     for (int w = 0; w < 2; ++w) {
       const void *fs[3] = {g_fft[n].plane[w], g_fft[n].row[w], g_fft[n].col[w]};
@@ -269,23 +290,43 @@ double entry_bytes(const Entry &e, Fam f) {
 
 qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS = 0, hipStream_t sto = nullptr);
 
-// transform passes are instantiated per lattice size: one launch per distinct N
+// Transform passes are instantiated per lattice size.  Entries are split by
+// size group; a group with one size uses that size's kernel, a group with
+// several sizes its multi-size kernel (KS = -2 - group), one launch per group.
 qfdtd_status run_fft_family(Fam f, std::vector<Entry> &es, bool dbl, hipStream_t sto) {
-  std::vector<int> sizes;
-  for (auto &e : es)
-    if (std::find(sizes.begin(), sizes.end(), e.c->N) == sizes.end()) sizes.push_back(e.c->N);
-  for (int N : sizes) {
+  for (int gi = 0; gi < 5; ++gi) {
     std::vector<Entry> sub;
+    int n0 = -1;
+    bool multi = false;
     for (auto &e : es)
-      if (e.c->N == N) sub.push_back(e);
-    QF_TRY(run_family(f, sub, dbl, -1, sto));
+      if (size_group(e.c->N) == gi) {
+        sub.push_back(e);
+        if (n0 < 0) n0 = e.c->N;
+        else if (e.c->N != n0) multi = true;
+      }
+    if (sub.empty()) continue;
+    if (multi && f == F_PLANE && !g_grp[gi].plane[dbl]) multi = false;
+    if (!multi) {
+      std::vector<int> sizes;
+      for (auto &e : sub)
+        if (std::find(sizes.begin(), sizes.end(), e.c->N) == sizes.end()) sizes.push_back(e.c->N);
+      for (int N : sizes) {
+        std::vector<Entry> one;
+        for (auto &e : sub)
+          if (e.c->N == N) one.push_back(e);
+        QF_TRY(run_family(f, one, dbl, -1, sto));
+      }
+    } else {
+      QF_TRY(run_family(f, sub, dbl, -2 - gi, sto));
+    }
   }
   return QFDTD_OK;
 }
 
 qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStream_t sto) {
   if (es.empty()) return QFDTD_OK;
-  if ((f == F_PLANE || f == F_ROW || f == F_COL) && KS != -1) return run_fft_family(f, es, dbl, sto);
+  if ((f == F_PLANE || f == F_ROW || f == F_COL) && KS >= 0) return run_fft_family(f, es, dbl, sto);
+  const int grp = KS <= -2 ? -2 - KS : -1;   // multi-size kernel of this group
   qfdtd_ctx *c0 = es[0].c;
   hipStream_t st = sto ? sto : c0->st;
   for (size_t base = 0; base < es.size(); base += MAX_LAUNCH) {
@@ -308,6 +349,8 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
       else if (f == F_ROW) l = K.row_lds[dbl];
       else if (f == F_COL) l = K.col_lds[dbl];
       if (l > lds) lds = l;
+      if (grp >= 0 && (f == F_PLANE || f == F_ROW || f == F_COL))
+        lds = g_grp_lds[grp][f == F_PLANE ? 0 : (f == F_ROW ? 1 : 2)][dbl];
       bytes += entry_bytes(e, f);
     }
     L.n = (int)cnt;
@@ -322,15 +365,19 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
     void *kargs[] = {(void *)&L};
     hipEvent_t ea = tix >= 0 ? c0->timer.pool[tix].a : nullptr;
     hipEvent_t eb = tix >= 0 ? c0->timer.pool[tix].b : nullptr;
+    const void *fplane = grp >= 0 ? g_grp[grp].plane[dbl] : K.plane[dbl];
+    const int ntplane = grp >= 0 ? g_grp[grp].plane_nt[dbl] : K.plane_nt;
+    const void *frow = grp >= 0 ? g_grp[grp].row[dbl] : K.row[dbl];
+    const void *fcol = grp >= 0 ? g_grp[grp].col[dbl] : K.col[dbl];
     switch (f) {
       case F_PLANE:
-        (void)hipExtLaunchKernel(K.plane[dbl], dim3(total), dim3(K.plane_nt), kargs, lds, st, ea, eb, 0);
+        (void)hipExtLaunchKernel(fplane, dim3(total), dim3(ntplane), kargs, lds, st, ea, eb, 0);
         break;
       case F_ROW:
-        (void)hipExtLaunchKernel(K.row[dbl], dim3(total), dim3(LINE_THREADS), kargs, lds, st, ea, eb, 0);
+        (void)hipExtLaunchKernel(frow, dim3(total), dim3(LINE_THREADS), kargs, lds, st, ea, eb, 0);
         break;
       case F_COL:
-        (void)hipExtLaunchKernel(K.col[dbl], dim3(total), dim3(LINE_THREADS), kargs, lds, st, ea, eb, 0);
+        (void)hipExtLaunchKernel(fcol, dim3(total), dim3(LINE_THREADS), kargs, lds, st, ea, eb, 0);
         break;
       case F_STENCIL:
         (void)hipExtLaunchKernel(stencil_kernel(dbl), dim3(total), dim3(RED_THREADS), kargs, 0, st, ea, eb, 0);
@@ -682,7 +729,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     delete c;
     return fail(nullptr, QFDTD_E_UNSUPPORTED_N, "no transform kernels for this N");
   }
-  c->plane = c->fft() && g_fft[N].plane[c->dbl ? 1 : 0] != nullptr;
+  c->plane = c->fft() && g_fft[N].plane[c->dbl ? 1 : 0] != nullptr && !(o.flags & QFDTD_F_ROWCOL);
   c->plane64 = c->fft() && g_fft[N].plane[1] != nullptr;
   c->nblk_red = (int)((n3 + 2047) / 2048);
   if (c->nblk_red > 1024) c->nblk_red = 1024;

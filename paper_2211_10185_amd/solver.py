@@ -78,7 +78,7 @@ class Solver:
                  vparams: Sequence[float] = (), knots=None, grid=None, precision: int = C64,
                  n_states: int = 3, sectors: Optional[Sequence[int]] = None,
                  measure_every: int = 50, trace: bool = False, torch_alloc: bool = True,
-                 single_stream: bool = False):
+                 single_stream: Optional[bool] = None, rowcol: Optional[bool] = None):
         torch = _torch()
         self.N, self.a, self.m, self.kinetic = int(N), float(a), float(m), int(kinetic)
         self.precision, self.k = int(precision), int(n_states)
@@ -94,7 +94,13 @@ class Solver:
             opt.sectors = ct.cast(sec, ct.POINTER(ct.c_int32))
         opt.measure_every = int(measure_every)
         opt.trace_energies = 1 if trace else 0
-        opt.flags = L.F_SINGLE_STREAM if single_stream else 0
+        if single_stream is None or rowcol is None:
+            from .autotune import schedule_for
+            tuned = schedule_for(self.N, self.kinetic, self.precision, self.k)
+            single_stream = tuned["single_stream"] if single_stream is None else single_stream
+            rowcol = tuned["rowcol"] if rowcol is None else rowcol
+        self.schedule = {"single_stream": bool(single_stream), "rowcol": bool(rowcol)}
+        opt.flags = (L.F_SINGLE_STREAM if single_stream else 0) | (L.F_ROWCOL if rowcol else 0)
         opt.hip_stream = ct.c_void_p(self.stream.cuda_stream)
         if self._alloc is not None:
             opt.dev_alloc = self._alloc.alloc
