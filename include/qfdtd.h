@@ -120,6 +120,8 @@ typedef struct {
                                      groups evolved on two internal streams */
 #define QFDTD_F_ROWCOL 2u         /* FFT kinds: use the row + three column pass schedule even
                                      where an x2-x3 plane fits in LDS (schedule autotuning) */
+#define QFDTD_F_NO_GRAPH 4u       /* qfdtd_evolve: launch every chunk directly instead of capturing
+                                     a chunk into a HIP graph once and replaying it */
 
 typedef struct qfdtd_ctx qfdtd_ctx;
 

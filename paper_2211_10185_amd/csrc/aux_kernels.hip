@@ -199,11 +199,13 @@ __global__ void __launch_bounds__(RED_THREADS) k_stencil(const LaunchList L) {
   const uint32_t mode = L.mode[e];
   const int N = d.N;
   const int ntx = (N + ST_TX - 1) / ST_TX, nty = (N + ST_TY - 1) / ST_TY, ncz = (N + ST_CZ - 1) / ST_CZ;
+  // states of one tile are adjacent in block order, so the potential (shared by
+  // all states) and the halo rows of neighbouring tiles are re-read from L2
   int t = blockIdx.x - L.tile_start[e];
+  const int s = t % d.k; t /= d.k;
   const int bx = t % ntx; t /= ntx;
   const int by = t % nty; t /= nty;
-  const int bz = t % ncz;
-  const int s = t / ncz;
+  const int bz = t;
   const int i3 = bx * ST_TX + (threadIdx.x & 63);
   const int i2 = by * ST_TY + (threadIdx.x >> 6);
   if (i3 >= N || i2 >= N) return;

@@ -54,8 +54,15 @@ __device__ __forceinline__ T kin_factor_t(const PassDesc &d, int i1, int i2, int
   if (d.kin == KIN_REL) {
     const T p2 = kt[i1] + kt[i2] + kt[i3];
     const T m = (T)d.m;
-    const T tk = p2 / (sqrt(p2 + m * m) + m);   // sqrt(p^2 + m^2) - m without cancellation
-    return exp(-(T)d.dt * tk) * (T)d.inv_n3;
+    if constexpr (sizeof(T) == 4) {
+      // single-instruction sqrt, reciprocal and 2^x (about 1 ulp each; the
+      // factor's relative error stays far below the complex64 state's)
+      const float tk = p2 * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(p2 + m * m) + m);
+      return __builtin_amdgcn_exp2f(-(float)d.dt * 1.4426950408889634f * tk) * (float)d.inv_n3;
+    } else {
+      const T tk = p2 / (sqrt(p2 + m * m) + m);   // sqrt(p^2 + m^2) - m without cancellation
+      return exp(-(T)d.dt * tk) * (T)d.inv_n3;
+    }
   }
   return kt[i1] * kt[i2] * kt[i3] * (T)d.inv_n3;
 }
@@ -182,6 +189,59 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_plane_t(const LaunchList
 
 // --------------------------------------------------------------- row pass
 
+// Steady-state row pass (inverse x3 -> x h^2 -> forward x3): first stage from
+// HBM, last stage to HBM, middle stages fused around the potential factor.
+template <typename T, int N, int NT, int RB, int P>
+__device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, const PassDesc &d, size_t voff0,
+                                           int nrows) {
+  using Rows = RowsGeo<RB, P>;
+  constexpr RPlan PL = plan_of<N, false>();
+  constexpr int M = PL.n - 1;
+  constexpr size_t N3 = (size_t)N * N * N;
+  const C<T> zero = mkc<T>(0, 0);
+  {
+    constexpr int R = PL.r[0];
+    C<T> v[SG<Rows, N, R, NT>::CAPQ][R];
+    st_read<T, N, R, 1, true, Rows, NT, 0>(v, tw, [&](int b, int n) { return b < nrows ? g[b * N + n] : zero; });
+    st_write<T, N, R, 1, Rows, NT>(v, [&](int b, int n, C<T> x) { buf[Rows::at(b, n)] = x; });
+    __syncthreads();
+  }
+  lds_stages<T, N, false, true, Rows, NT, 1, M>(buf, tw);
+  {
+    constexpr int R = PL.r[M];
+    constexpr int NSL = ns_before<N, false, M>();
+    using SS = SG<Rows, N, R, NT>;
+    C<T> v[SS::CAPQ][R];
+    st_read<T, N, R, NSL, true, Rows, NT, tw_off<N, false, M>()>(v, tw, [&](int b, int n) { return buf[Rows::at(b, n)]; });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SS::CAPQ; ++q) {
+      if (SS::active(q)) {
+        int j, b;
+        SS::jb(q, j, b);
+        if (b < nrows) {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            v[q][r] = vmul_t<T>(v[q][r], d.h2fac, d.vcomplex, (voff0 + (size_t)b * N + j + r * SS::NR) % N3);
+        }
+        Dft<R, false, C<T>>::run(v[q]);
+      }
+    }
+    st_write<T, N, R, 1, Rows, NT>(v, [&](int b, int n, C<T> x) { buf[Rows::at(b, n)] = x; });
+    __syncthreads();
+  }
+  lds_stages<T, N, true, false, Rows, NT, 1, M>(buf, tw);
+  {
+    constexpr int R = plan_of<N, true>().r[M];
+    constexpr int NSL = ns_before<N, true, M>();
+    C<T> v[SG<Rows, N, R, NT>::CAPQ][R];
+    st_read<T, N, R, NSL, false, Rows, NT, tw_off<N, true, M>()>(v, tw, [&](int b, int n) { return buf[Rows::at(b, n)]; });
+    st_write<T, N, R, NSL, Rows, NT>(v, [&](int b, int n, C<T> x) {
+      if (b < nrows) g[b * N + n] = x;
+    });
+  }
+}
+
 // Tile = RB consecutive x3 rows over all states (the last tile may be short).
 template <typename T, int N, int NT>
 __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsigned char *smem) {
@@ -199,6 +259,13 @@ __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsi
   C<T> *g = (C<T> *)d.psi + (size_t)row0 * N;
   // site offset of the tile's first row within its state; (voff0 + idx) % N^3 wraps at state boundaries
   const size_t voff0 = (size_t)(row0 % (long long)(N * N)) * N;
+  if constexpr (plan_of<N, false>().n >= 2) {
+    if (mode == (M_INV | M_MID | M_FWD)) {
+      __syncthreads();
+      row_steady<T, N, NT, RB, P>(buf, tw, g, d, voff0, nrows);
+      return;
+    }
+  }
   for (int idx = threadIdx.x; idx < RB * N; idx += NT) {
     const int r = idx / N, c = idx - r * N;
     C<T> v = mkc<T>(0, 0);
@@ -298,6 +365,34 @@ __device__ __forceinline__ void col_steady(C<T> *buf, const C<T> *tw, C<T> *g, s
   }
 }
 
+// Column pass in one direction only (forward, or inverse with optional 1/N^3):
+// first stage from HBM, last stage to HBM.
+template <typename T, int N, int NT, class Geo, bool INV>
+__device__ __forceinline__ void col_single(C<T> *buf, const C<T> *tw, C<T> *g, size_t S, int nc, T post) {
+  constexpr RPlan PL = plan_of<N, false>();
+  constexpr int M = PL.n - 1;
+  constexpr int TC = Geo::nlines;
+  const C<T> zero = mkc<T>(0, 0);
+  {
+    constexpr int R = PL.r[0];
+    C<T> v[SG<Geo, N, R, NT>::CAPQ][R];
+    st_read<T, N, R, 1, INV, Geo, NT, 0>(
+        v, tw, [&](int b, int n) { return (N % TC == 0 || b < nc) ? g[(size_t)n * S + b] : zero; });
+    st_write<T, N, R, 1, Geo, NT>(v, [&](int b, int n, C<T> x) { buf[Geo::at(b, n)] = x; });
+    __syncthreads();
+  }
+  lds_stages<T, N, false, INV, Geo, NT, 1, M>(buf, tw);
+  {
+    constexpr int R = PL.r[M];
+    constexpr int NSL = ns_before<N, false, M>();
+    C<T> v[SG<Geo, N, R, NT>::CAPQ][R];
+    st_read<T, N, R, NSL, INV, Geo, NT, tw_off<N, false, M>()>(v, tw, [&](int b, int n) { return buf[Geo::at(b, n)]; });
+    st_write<T, N, R, NSL, Geo, NT>(v, [&](int b, int n, C<T> x) {
+      if (N % TC == 0 || b < nc) g[(size_t)n * S + b] = cscale(x, post);
+    });
+  }
+}
+
 // Tile = TC contiguous x3 columns at one position of the other transverse
 // axis; all N elements along the transform axis (x1 if M_AXIS1, else x2).
 template <typename T, int N, int NT>
@@ -321,9 +416,16 @@ __device__ __forceinline__ void col_body(const LaunchList &L, int e, int t, unsi
   C<T> *g = (C<T> *)d.psi + (size_t)s * N * N * N + (size_t)o * OS + c0;
   using Geo = TileGeo<TC, PC>;
   if constexpr (plan_of<N, false>().n >= 2) {
-    if ((mode & (M_FWD | M_KIN | M_INV | M_SCALE)) == (M_FWD | M_KIN | M_INV)) {
-      const int nc = (N - c0) < TC ? (N - c0) : TC;
+    const int nc = (N - c0) < TC ? (N - c0) : TC;
+    const uint32_t m3 = mode & (M_FWD | M_KIN | M_INV);
+    if (m3 == (M_FWD | M_KIN | M_INV) && !(mode & M_SCALE)) {
       col_steady<T, N, NT, Geo>(buf, tw, g, S, d, ax1, o, c0, nc);
+      return;
+    }
+    if (m3 == M_FWD || m3 == M_INV) {
+      const T post = (mode & M_SCALE) ? (T)d.inv_n3 : (T)1;
+      if (m3 == M_FWD) col_single<T, N, NT, Geo, false>(buf, tw, g, S, nc, post);
+      else col_single<T, N, NT, Geo, true>(buf, tw, g, S, nc, post);
       return;
     }
   }

@@ -163,6 +163,8 @@ struct qfdtd_ctx {
   int gk[2] = {0, 0};           // states per group
   hipStream_t gst[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  bool graphs = true;           // capture a steady chunk (passes + orthonormalisation) once, replay it
+  std::vector<std::pair<int, hipGraphExec_t>> chunk_graphs;   // keyed by steps in the chunk
   int nblk_red = 1;
   double cur_dt = -1.0;
   bool fresh = true;
@@ -369,19 +371,17 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
     const int ntplane = grp >= 0 ? g_grp[grp].plane_nt[dbl] : K.plane_nt;
     const void *frow = grp >= 0 ? g_grp[grp].row[dbl] : K.row[dbl];
     const void *fcol = grp >= 0 ? g_grp[grp].col[dbl] : K.col[dbl];
+    // timed launches carry their event pair in the dispatch; untimed ones use the
+    // plain launch, which can also be captured into a graph
+    auto go = [&](const void *fn, int nt, size_t sh) {
+      if (tix >= 0) (void)hipExtLaunchKernel(fn, dim3(total), dim3(nt), kargs, sh, st, ea, eb, 0);
+      else (void)hipLaunchKernel(fn, dim3(total), dim3(nt), kargs, sh, st);
+    };
     switch (f) {
-      case F_PLANE:
-        (void)hipExtLaunchKernel(fplane, dim3(total), dim3(ntplane), kargs, lds, st, ea, eb, 0);
-        break;
-      case F_ROW:
-        (void)hipExtLaunchKernel(frow, dim3(total), dim3(LINE_THREADS), kargs, lds, st, ea, eb, 0);
-        break;
-      case F_COL:
-        (void)hipExtLaunchKernel(fcol, dim3(total), dim3(LINE_THREADS), kargs, lds, st, ea, eb, 0);
-        break;
-      case F_STENCIL:
-        (void)hipExtLaunchKernel(stencil_kernel(dbl), dim3(total), dim3(RED_THREADS), kargs, 0, st, ea, eb, 0);
-        break;
+      case F_PLANE: go(fplane, ntplane, lds); break;
+      case F_ROW: go(frow, LINE_THREADS, lds); break;
+      case F_COL: go(fcol, LINE_THREADS, lds); break;
+      case F_STENCIL: go(stencil_kernel(dbl), RED_THREADS, 0); break;
       case F_PARITY: launch_parity(L, total, dbl, st); break;
       case F_TO64: launch_to64(L, total, dbl, st); break;
       case F_GRAM: launch_gram(L, total, KS, dbl, st); break;
@@ -630,6 +630,53 @@ qfdtd_status batch_evolve_impl(qfdtd_ctx *const *members, int32_t n, const int64
   for (auto *c : ms)
     if (c->fresh) fr.push_back(c);
   QF_TRY(orthonormalise(fr));
+  // A single context replays a captured graph of each chunk shape (steps in
+  // the chunk) after its first use; kernel arguments are captured by value and
+  // point at buffers that live as long as the context.
+  if (n == 1 && ms[0]->graphs && !ms[0]->trace_on && ms[0]->timer.every <= 0) {
+    qfdtd_ctx *c = ms[0];
+    int64_t rem0 = rem[0];
+    while (rem0 > 0) {
+      const int cn = (int)(rem0 < c->K ? rem0 : c->K);
+      hipGraphExec_t ex = nullptr;
+      for (auto &g : c->chunk_graphs)
+        if (g.first == cn) ex = g.second;
+      if (!ex) {
+        hipGraph_t gr = nullptr;
+        if (hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+          (void)hipGetLastError();
+          c->graphs = false;
+          break;
+        }
+        std::vector<qfdtd_ctx *> one{c};
+        std::vector<int> nn{cn};
+        qfdtd_status st1 = run_chunk(one, nn);
+        if (st1 == QFDTD_OK) st1 = orthonormalise(one);
+        hipError_t ee = hipStreamEndCapture(c->st, &gr);
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(c->st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+          hipGraph_t junk = nullptr;
+          (void)hipStreamEndCapture(c->st, &junk);
+          if (junk) (void)hipGraphDestroy(junk);
+          ee = hipErrorUnknown;
+        }
+        if (st1 != QFDTD_OK || ee != hipSuccess || !gr ||
+            hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) != hipSuccess) {
+          if (gr) (void)hipGraphDestroy(gr);
+          (void)hipGetLastError();
+          c->graphs = false;   // fall back to direct launches for this context
+          c->cur = 0;          // nothing captured ran; the states are where the chunk found them
+          c->err.clear();
+          break;
+        }
+        (void)hipGraphDestroy(gr);
+        c->chunk_graphs.push_back({cn, ex});
+      }
+      QF_HIP(c, hipGraphLaunch(ex, c->st));
+      rem0 -= cn;
+    }
+    rem[0] = rem0;
+  }
   for (;;) {
     std::vector<qfdtd_ctx *> act;
     std::vector<int> cn;
@@ -735,6 +782,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   if (c->nblk_red > 1024) c->nblk_red = 1024;
   if (c->nblk_red < 1) c->nblk_red = 1;
   c->trace_on = o.trace_energies ? 1 : 0;
+  c->graphs = !(o.flags & QFDTD_F_NO_GRAPH);
   c->trace_cap = c->trace_on ? 4096 : 0;
 
   auto bail = [&](qfdtd_status s, const std::string &msg) {
@@ -1083,6 +1131,8 @@ void qfdtd_destroy(qfdtd_ctx *c) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
+  for (auto &g : c->chunk_graphs) (void)hipGraphExecDestroy(g.second);
+  c->chunk_graphs.clear();
   for (int g = 0; g < 2; ++g) {
     if (c->gst[g]) { (void)hipStreamSynchronize(c->gst[g]); (void)hipStreamDestroy(c->gst[g]); }
     if (c->ev_join[g]) (void)hipEventDestroy(c->ev_join[g]);

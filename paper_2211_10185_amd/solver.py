@@ -78,7 +78,8 @@ class Solver:
                  vparams: Sequence[float] = (), knots=None, grid=None, precision: int = C64,
                  n_states: int = 3, sectors: Optional[Sequence[int]] = None,
                  measure_every: int = 50, trace: bool = False, torch_alloc: bool = True,
-                 single_stream: Optional[bool] = None, rowcol: Optional[bool] = None):
+                 single_stream: Optional[bool] = None, rowcol: Optional[bool] = None,
+                 graphs: bool = True):
         torch = _torch()
         self.N, self.a, self.m, self.kinetic = int(N), float(a), float(m), int(kinetic)
         self.precision, self.k = int(precision), int(n_states)
@@ -100,7 +101,8 @@ class Solver:
             single_stream = tuned["single_stream"] if single_stream is None else single_stream
             rowcol = tuned["rowcol"] if rowcol is None else rowcol
         self.schedule = {"single_stream": bool(single_stream), "rowcol": bool(rowcol)}
-        opt.flags = (L.F_SINGLE_STREAM if single_stream else 0) | (L.F_ROWCOL if rowcol else 0)
+        opt.flags = ((L.F_SINGLE_STREAM if single_stream else 0) | (L.F_ROWCOL if rowcol else 0)
+                     | (0 if graphs else L.F_NO_GRAPH))
         opt.hip_stream = ct.c_void_p(self.stream.cuda_stream)
         if self._alloc is not None:
             opt.dev_alloc = self._alloc.alloc

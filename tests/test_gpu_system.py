@@ -237,3 +237,28 @@ def test_config3_full_run_properties():
     assert np.linalg.norm(refl(psi[2], (2,)) + psi[2]) < 1e-4
     # the chunk trace has settled
     assert np.max(np.abs(tr[-1] - tr[-2])) < 1e-6
+
+
+@pytest.mark.parametrize("kind,N,prec", [(S.K_NR_SIN2, 32, 1), (S.K_FDTD, 32, 0), (S.K_NR_SIN2, 128, 0),
+                                         (S.K_REL, 144, 0)])
+def test_graph_replays_match_direct_launches(kind, N, prec):
+    # the captured chunk is replayed several times, with eager work and synchronisation in between;
+    # every replay must give the bits of the directly launched run
+    from paper_2211_10185_amd.solver import Solver
+    p = prob(kind, N, prec=prec, K=20)
+    if kind == S.K_REL:
+        p.vkind, p.vparams, p.a, p.m, p.dt = S.V_CORNELL, (0.4, 0.2, 0.025), 0.05, 1.5, 0.05 / 8
+    a = solver(p, graphs=True)
+    b = solver(p, graphs=False)
+    init = p.init_states()
+    a.set_states(init)
+    b.set_states(init)
+    for rep in range(4):
+        a.evolve(60, p.dt)
+        b.evolve(60, p.dt)
+        Ea, pa = a.states()
+        Eb, pb = b.states()
+        assert np.array_equal(Ea, Eb), rep
+        assert np.array_equal(pa, pb), rep
+    a.close()
+    b.close()
