@@ -121,28 +121,53 @@ __global__ void k_dt_tables(const double *v64, int vcomplex, size_t N3, double d
 // psi' = A psi + B c (sum of 6 neighbours - 6 psi), c = dt/(2 m a^2),
 // A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2); walls are ghost zeros.
 //
-// Tile = 64 (x3) x 4 (x2) columns of one state over a chunk of ST_CZ planes
-// along x1.  Each thread marches along x1 keeping psi at i1-1, i1, i1+1 in
-// registers, so every site is read once from memory per sweep; the four
-// in-plane neighbours are the centres of neighbouring lanes and rows (L1).
-constexpr int ST_TX = 64, ST_TY = RED_THREADS / 64, ST_CZ = 16;
+// Tile = 64 (x3) x 16 (x2) columns of one state over ST_CZ planes along x1.
+// Each wave owns 4 consecutive x2 rows, one x3 column per lane, and marches
+// along x1 keeping psi at i1-1, i1, i1+1 of its 4 sites in registers.  x2
+// neighbours come from the thread's own rows (memory only for the rows just
+// outside its 4), x3 neighbours from the adjacent lanes by wavefront shifts
+// (memory only at the tile's x3 edges), so each site is read from memory about
+// once per sweep.  Loads of ST_ZU planes are issued together.
+constexpr int ST_TX = 64, ST_RPT = 4, ST_TY = (RED_THREADS / 64) * ST_RPT, ST_CZ = 8, ST_ZU = 2;
 
 __host__ __device__ inline int stencil_tiles(int N, int k) {
   return k * ((N + ST_TX - 1) / ST_TX) * ((N + ST_TY - 1) / ST_TY) * ((N + ST_CZ - 1) / ST_CZ);
 }
 
+// value of lane l-1 (DPP wave shift right by one; lane 0 gets 0)
+__device__ __forceinline__ float lane_prev(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, true));
+}
+// value of lane l+1 (DPP wave shift left by one; lane 63 gets 0)
+__device__ __forceinline__ float lane_next(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double lane_prev(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_next(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, bool VC> struct VType { using type = T; };
+template <typename T> struct VType<T, true> { using type = C<T>; };
+
 template <typename T, bool VC>
-__device__ __forceinline__ C<T> fdtd_update(C<T> cur, C<T> acc, const void *__restrict__ vtab, int off, T c, T hdt) {
+__device__ __forceinline__ C<T> fdtd_update(C<T> cur, C<T> acc, typename VType<T, VC>::type V, T c, T hdt) {
   if constexpr (VC) {
-    const C<T> V = ((const C<T> *)vtab)[off];
     // B = 1/(1 + dt V/2), A = (1 - dt V/2) B
-    const T dr = (T)1 + hdt * V.x, di = hdt * V.y;
-    const T den = (T)1 / (dr * dr + di * di);
+    const T dr = fmaT(hdt, V.x, (T)1), di = hdt * V.y;
+    const T den = (T)1 / fmaT(dr, dr, di * di);
     const C<T> B = mkc<T>(dr * den, -di * den);
-    const C<T> A = cmul(mkc<T>((T)1 - hdt * V.x, -hdt * V.y), B);
+    const C<T> A = cmul(mkc<T>(fmaT(-hdt, V.x, (T)1), -hdt * V.y), B);
     return cadd(cmul(A, cur), cmul(B, cscale(acc, c)));
   } else {
-    const T V = ((const T *)vtab)[off];
     const T B = (T)1 / fmaT(hdt, V, (T)1);
     const T A = fmaT(-hdt, V, (T)1) * B;
     const T Bc = B * c;
@@ -150,43 +175,75 @@ __device__ __forceinline__ C<T> fdtd_update(C<T> cur, C<T> acc, const void *__re
   }
 }
 
-// z-march over one column; ZU planes per group: all loads of a group are
-// issued before its stores so that each thread keeps several HBM reads in flight
 template <typename T, bool VC>
-__device__ __forceinline__ void stencil_column(const C<T> *__restrict__ sp, C<T> *__restrict__ dp,
-                                               const void *__restrict__ vtab, int N, int i2, int i3, int z0,
-                                               int z1, T c, T hdt) {
-  constexpr int ZU = 8;
+__device__ __forceinline__ typename VType<T, VC>::type load_v(const void *__restrict__ vtab, int off) {
+  return ((const typename VType<T, VC>::type *)vtab)[off];
+}
+
+template <typename T, bool VC>
+__device__ __forceinline__ void stencil_tile(const C<T> *__restrict__ sp, C<T> *__restrict__ dp,
+                                             const void *__restrict__ vtab, int N, int y0, int i3, int lane,
+                                             int z0, int z1, T c, T hdt) {
   const int N2 = N * N;
   const C<T> zero = mkc<T>(0, 0);
-  int off = (z0 * N + i2) * N + i3;
-  C<T> prev = z0 > 0 ? sp[off - N2] : zero;
-  C<T> cur = sp[off];
-  const bool xl = i3 > 0, xr = i3 < N - 1, yl = i2 > 0, yr = i2 < N - 1;
-  for (int z = z0; z < z1; z += ZU) {
-    C<T> nx[ZU], nb[ZU];
+  const bool xin = i3 < N;
+  bool rin[ST_RPT];
 #pragma unroll
-    for (int u = 0; u < ZU; ++u) {
+  for (int r = 0; r < ST_RPT; ++r) rin[r] = xin && (y0 + r < N);
+  const bool up_ok = xin && y0 > 0, dn_ok = xin && y0 + ST_RPT < N;
+  // x3 neighbour outside the wave: lane 0 needs i3-1, lane 63 needs i3+1
+  const int xe_off = lane == 0 ? -1 : 1;
+  const bool xe_mem = (lane == 0 && xin && i3 > 0) || (lane == 63 && i3 + 1 < N);
+  const bool xr_wall = i3 + 1 >= N;
+  using VT = typename VType<T, VC>::type;
+  VT vzero;
+  if constexpr (VC) vzero = zero; else vzero = (T)0;
+  int off0 = (z0 * N + y0) * N + i3;                           // site (z0, y0, i3)
+  C<T> prev[ST_RPT], cur[ST_RPT];
+#pragma unroll
+  for (int r = 0; r < ST_RPT; ++r) {
+    prev[r] = (rin[r] && z0 > 0) ? sp[off0 + r * N - N2] : zero;
+    cur[r] = rin[r] ? sp[off0 + r * N] : zero;
+  }
+  for (int z = z0; z < z1; z += ST_ZU) {
+    C<T> nx[ST_ZU][ST_RPT], up[ST_ZU], dn[ST_ZU], xe[ST_ZU][ST_RPT];
+    VT V[ST_ZU][ST_RPT];
+#pragma unroll
+    for (int u = 0; u < ST_ZU; ++u) {
       const int zz = z + u;
-      const int o = off + u * N2;
-      nx[u] = (zz + 1 < N) ? sp[o + N2] : zero;
-      C<T> a = zero;
-      if (zz < z1) {
-        if (xl) a = cadd(a, sp[o - 1]);
-        if (xr) a = cadd(a, sp[o + 1]);
-        if (yl) a = cadd(a, sp[o - N]);
-        if (yr) a = cadd(a, sp[o + N]);
+      const int o = off0 + (zz - z0) * N2;
+      const bool zin = zz < z1;
+#pragma unroll
+      for (int r = 0; r < ST_RPT; ++r) {
+        nx[u][r] = (rin[r] && zz + 1 < N && zin) ? sp[o + r * N + N2] : zero;
+        V[u][r] = (rin[r] && zin) ? load_v<T, VC>(vtab, o + r * N) : vzero;
+        xe[u][r] = (rin[r] && zin && xe_mem) ? sp[o + r * N + xe_off] : zero;
       }
-      nb[u] = a;
+      up[u] = (up_ok && zin) ? sp[o - N] : zero;
+      dn[u] = (dn_ok && zin) ? sp[o + ST_RPT * N] : zero;
     }
 #pragma unroll
-    for (int u = 0; u < ZU; ++u) {
-      if (z + u < z1) {
-        const C<T> acc = cadd(csub(cadd(prev, nx[u]), cscale(cur, (T)6)), nb[u]);
-        dp[off] = fdtd_update<T, VC>(cur, acc, vtab, off, c, hdt);
-        prev = cur;
-        cur = nx[u];
-        off += N2;
+    for (int u = 0; u < ST_ZU; ++u) {
+      if (z + u >= z1) break;
+      const int o = off0 + (z + u - z0) * N2;
+#pragma unroll
+      for (int r = 0; r < ST_RPT; ++r) {
+        // x3 neighbours: adjacent lanes, or memory at the wave's edges, or the wall
+        C<T> l = mkc<T>(lane_prev(cur[r].x), lane_prev(cur[r].y));
+        C<T> rr = mkc<T>(lane_next(cur[r].x), lane_next(cur[r].y));
+        if (lane == 0) l = xe[u][r];
+        if (lane == 63) rr = xe[u][r];
+        if (xr_wall) rr = zero;
+        const C<T> yu = r > 0 ? cur[r - 1] : up[u];
+        const C<T> yd = r < ST_RPT - 1 ? cur[r + 1] : dn[u];
+        C<T> acc = csub(cadd(prev[r], nx[u][r]), cscale(cur[r], (T)6));
+        acc = cadd(acc, cadd(cadd(l, rr), cadd(yu, yd)));
+        if (rin[r]) dp[o + r * N] = fdtd_update<T, VC>(cur[r], acc, V[u][r], c, hdt);
+      }
+#pragma unroll
+      for (int r = 0; r < ST_RPT; ++r) {
+        prev[r] = cur[r];
+        cur[r] = nx[u][r];
       }
     }
   }
@@ -198,7 +255,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_stencil(const LaunchList L) {
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
   const int N = d.N;
-  const int ntx = (N + ST_TX - 1) / ST_TX, nty = (N + ST_TY - 1) / ST_TY, ncz = (N + ST_CZ - 1) / ST_CZ;
+  const int ntx = (N + ST_TX - 1) / ST_TX, nty = (N + ST_TY - 1) / ST_TY;
   // states of one tile are adjacent in block order, so the potential (shared by
   // all states) and the halo rows of neighbouring tiles are re-read from L2
   int t = blockIdx.x - L.tile_start[e];
@@ -206,17 +263,19 @@ __global__ void __launch_bounds__(RED_THREADS) k_stencil(const LaunchList L) {
   const int bx = t % ntx; t /= ntx;
   const int by = t % nty; t /= nty;
   const int bz = t;
-  const int i3 = bx * ST_TX + (threadIdx.x & 63);
-  const int i2 = by * ST_TY + (threadIdx.x >> 6);
-  if (i3 >= N || i2 >= N) return;
+  const int lane = threadIdx.x & 63;
+  const int i3 = bx * ST_TX + lane;
+  const int y0 = by * ST_TY + (threadIdx.x >> 6) * ST_RPT;
   const size_t N3 = (size_t)N * N * N;
   const C<T> *sp = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi) + (size_t)s * N3;
   C<T> *dp = (C<T> *)((mode & M_SWAP) ? d.psi : d.alt) + (size_t)s * N3;
   const T c = (T)d.stencil_c, hdt = (T)(0.5 * d.dt);
   const int z0 = bz * ST_CZ;
   const int z1 = (z0 + ST_CZ < N) ? z0 + ST_CZ : N;
-  if (d.vcomplex) stencil_column<T, true>(sp, dp, d.vtab, N, i2, i3, z0, z1, c, hdt);
-  else stencil_column<T, false>(sp, dp, d.vtab, N, i2, i3, z0, z1, c, hdt);
+  // every lane of the wave takes part (the lane shifts need the whole wave),
+  // lanes and rows outside the lattice neither load nor store
+  if (d.vcomplex) stencil_tile<T, true>(sp, dp, d.vtab, N, y0, i3, lane, z0, z1, c, hdt);
+  else stencil_tile<T, false>(sp, dp, d.vtab, N, y0, i3, lane, z0, z1, c, hdt);
 }
 
 // ---------------------------------------------------------------- parity

@@ -78,12 +78,30 @@ __device__ __forceinline__ void load_tw(C<T> *tw, const PassDesc &d) {
 // first stage read from HBM, the last stage written to HBM, and the inverse-x3
 // last stage, the potential factor and the forward-x3 first stage fused in
 // registers.  The inverse uses the radix plan, the forward its reverse.
-template <typename T, int N, int NT, int P>
+template <typename T, bool VC> struct FacT { using type = T; };
+template <typename T> struct FacT<T, true> { using type = C<T>; };
+
+template <typename T, int N, int NT, int P, bool VC>
 __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, const PassDesc &d, size_t voff) {
   using Rows = RowsGeo<N, P>;
   using Cols = ColsGeo<N, P>;
   constexpr RPlan PL = plan_of<N, false>();
   constexpr int M = PL.n - 1;
+  // potential factors of the fused middle stage, fetched before any transform
+  // work so their latency overlaps the inverse transforms
+  constexpr int RMID = PL.r[M];
+  using SMID = SG<Rows, N, RMID, NT>;
+  using F = typename FacT<T, VC>::type;
+  F hq[SMID::CAPQ][RMID];
+#pragma unroll
+  for (int q = 0; q < SMID::CAPQ; ++q) {
+    if (SMID::active(q)) {
+      int j, b;
+      SMID::jb(q, j, b);
+#pragma unroll
+      for (int r = 0; r < RMID; ++r) hq[q][r] = ((const F *)d.h2fac)[voff + (size_t)b * N + j + r * SMID::NR];
+    }
+  }
   {
     constexpr int R = PL.r[0];
     C<T> v[SG<Cols, N, R, NT>::CAPQ][R];
@@ -106,8 +124,10 @@ __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, 
         int j, b;
         S::jb(q, j, b);
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-          v[q][r] = vmul_t<T>(v[q][r], d.h2fac, d.vcomplex, voff + (size_t)b * N + j + r * S::NR);
+        for (int r = 0; r < R; ++r) {
+          if constexpr (VC) v[q][r] = cmul(v[q][r], hq[q][r]);
+          else v[q][r] = cscale(v[q][r], hq[q][r]);
+        }
         Dft<R, false, C<T>>::run(v[q]);
       }
     }
@@ -143,7 +163,8 @@ __device__ __forceinline__ void plane_body(const LaunchList &L, int e, int t, un
   if constexpr (plan_of<N, false>().n >= 2) {
     if (mode == (M_INV | M_MID | M_FWD)) {
       __syncthreads();
-      plane_steady<T, N, NT, P>(pl, tw, g, d, voff);
+      if (d.vcomplex) plane_steady<T, N, NT, P, true>(pl, tw, g, d, voff);
+      else plane_steady<T, N, NT, P, false>(pl, tw, g, d, voff);
       return;
     }
   }

@@ -17,6 +17,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <mutex>
+#include <atomic>
 
 #include "common.h"
 #include "qfdtd.h"
@@ -130,6 +132,34 @@ hipError_t fft_table_init() {
   return hipSuccess;
 }
 
+// Captured chunks of multi-member batches: key = (member serial, steps) for
+// every member in batch order.  A key seen once is only recorded (exec null);
+// its second use captures, later uses replay, so chunk shapes that occur once
+// (a serving loop between admissions) never pay for a capture.  Entries that
+// hold a destroyed member are dropped; the cache keeps at most MAX_BATCH_GRAPHS.
+struct BatchGraph {
+  std::vector<std::pair<uint64_t, int>> key;
+  hipGraphExec_t exec;
+};
+constexpr size_t MAX_BATCH_GRAPHS = 128;
+std::vector<BatchGraph> g_batch_graphs;
+std::mutex g_batch_mu;
+std::atomic<uint64_t> g_next_serial{1};
+
+void drop_batch_graphs(uint64_t serial) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (size_t i = 0; i < g_batch_graphs.size();) {
+    bool hit = false;
+    for (auto &kv : g_batch_graphs[i].key) hit = hit || kv.first == serial;
+    if (hit) {
+      if (g_batch_graphs[i].exec) (void)hipGraphExecDestroy(g_batch_graphs[i].exec);
+      g_batch_graphs.erase(g_batch_graphs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
 int plane_tiles(int N, int k) { return k * N; }
 int row_tiles(int N, int k) {
   const long long rows = (long long)k * N * N;
@@ -163,6 +193,7 @@ struct qfdtd_ctx {
   int gk[2] = {0, 0};           // states per group
   hipStream_t gst[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  uint64_t serial = 0;          // unique per context, never reused (keys of batch graphs)
   bool graphs = true;           // capture a steady chunk (passes + orthonormalisation) once, replay it
   std::vector<std::pair<int, hipGraphExec_t>> chunk_graphs;   // keyed by steps in the chunk
   int nblk_red = 1;
@@ -677,6 +708,10 @@ qfdtd_status batch_evolve_impl(qfdtd_ctx *const *members, int32_t n, const int64
     }
     rem[0] = rem0;
   }
+  // Several members: capture each distinct chunk shape (active members and their
+  // step counts) once and replay it, when every member allows graphs.
+  bool bgraph = n > 1;
+  for (auto *c : ms) bgraph = bgraph && c->graphs && !c->trace_on && c->timer.every <= 0;
   for (;;) {
     std::vector<qfdtd_ctx *> act;
     std::vector<int> cn;
@@ -686,6 +721,62 @@ qfdtd_status batch_evolve_impl(qfdtd_ctx *const *members, int32_t n, const int64
         cn.push_back((int)(rem[j] < ms[j]->K ? rem[j] : ms[j]->K));
       }
     if (act.empty()) break;
+    if (bgraph) {
+      std::vector<std::pair<uint64_t, int>> key;
+      for (size_t j = 0; j < act.size(); ++j) key.push_back({act[j]->serial, cn[j]});
+      std::lock_guard<std::mutex> lk(g_batch_mu);
+      BatchGraph *hit = nullptr;
+      for (auto &bg : g_batch_graphs)
+        if (bg.key == key) hit = &bg;
+      bool replay = false;
+      if (!hit) {
+        if (g_batch_graphs.size() >= MAX_BATCH_GRAPHS) {
+          if (g_batch_graphs.front().exec) (void)hipGraphExecDestroy(g_batch_graphs.front().exec);
+          g_batch_graphs.erase(g_batch_graphs.begin());
+        }
+        g_batch_graphs.push_back({key, nullptr});     // first sighting: direct launches below
+      } else if (hit->exec) {
+        replay = true;
+      } else {
+        hipStream_t st0 = act[0]->st;
+        hipGraph_t gr = nullptr;
+        hipGraphExec_t ex = nullptr;
+        std::vector<int> saved_cur;
+        for (auto *c : act) saved_cur.push_back(c->cur);
+        bool ok = hipStreamBeginCapture(st0, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+          qfdtd_status s1 = run_chunk(act, cn);
+          if (s1 == QFDTD_OK) s1 = orthonormalise(act);
+          hipError_t ee = hipStreamEndCapture(st0, &gr);
+          hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+          if (hipStreamIsCapturing(st0, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(st0, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            ee = hipErrorUnknown;
+          }
+          ok = s1 == QFDTD_OK && ee == hipSuccess && gr &&
+               hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0) == hipSuccess;
+          if (gr) (void)hipGraphDestroy(gr);
+        }
+        if (!ok) {
+          // nothing captured ran: the states are where the chunk found them
+          for (size_t j = 0; j < act.size(); ++j) { act[j]->cur = saved_cur[j]; act[j]->err.clear(); }
+          (void)hipGetLastError();
+          bgraph = false;     // this call continues with direct launches
+        } else {
+          hit->exec = ex;
+          replay = true;
+        }
+      }
+      if (replay) {
+        QF_HIP(act[0], hipGraphLaunch(hit->exec, act[0]->st));
+        size_t q = 0;
+        for (size_t j = 0; j < ms.size(); ++j)
+          if (rem[j] > 0) rem[j] -= cn[q++];
+        continue;
+      }
+    }
     QF_TRY(run_chunk(act, cn));
     QF_TRY(orthonormalise(act));
     std::vector<qfdtd_ctx *> tr;
@@ -783,6 +874,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   if (c->nblk_red < 1) c->nblk_red = 1;
   c->trace_on = o.trace_energies ? 1 : 0;
   c->graphs = !(o.flags & QFDTD_F_NO_GRAPH);
+  c->serial = g_next_serial.fetch_add(1);
   c->trace_cap = c->trace_on ? 4096 : 0;
 
   auto bail = [&](qfdtd_status s, const std::string &msg) {
@@ -1133,6 +1225,7 @@ void qfdtd_destroy(qfdtd_ctx *c) {
   }
   for (auto &g : c->chunk_graphs) (void)hipGraphExecDestroy(g.second);
   c->chunk_graphs.clear();
+  drop_batch_graphs(c->serial);
   for (int g = 0; g < 2; ++g) {
     if (c->gst[g]) { (void)hipStreamSynchronize(c->gst[g]); (void)hipStreamDestroy(c->gst[g]); }
     if (c->ev_join[g]) (void)hipEventDestroy(c->ev_join[g]);

@@ -262,3 +262,31 @@ def test_graph_replays_match_direct_launches(kind, N, prec):
         assert np.array_equal(pa, pb), rep
     a.close()
     b.close()
+
+
+def test_batch_graph_replays_match_direct_launches():
+    # a batch is captured on the second use of a chunk shape and replayed after that; members
+    # that drop out (fewer steps) change the shape.  Every call must give the direct-launch bits.
+    from paper_2211_10185_amd.solver import batch_evolve
+    probs = [prob(S.K_NR_SIN2, 48, seed=1, K=10), prob(S.K_FDTD, 40, seed=4, K=10),
+             prob(S.K_NR_P2, 36, prec=0, seed=3, K=10)]
+    steps = [40, 30, 25]
+    ga = [solver(p, graphs=True) for p in probs]
+    gb = [solver(p, graphs=False) for p in probs]
+    for s, p in zip(ga + gb, probs + probs):
+        s.set_states(p.init_states())
+    for rep in range(4):
+        batch_evolve(ga, steps, [p.dt for p in probs])
+        batch_evolve(gb, steps, [p.dt for p in probs])
+        for sa, sb in zip(ga, gb):
+            Ea, pa = sa.states()
+            Eb, pb = sb.states()
+            assert np.array_equal(Ea, Eb), rep
+            assert np.array_equal(pa, pb), rep
+    # a dt change between replays reaches the captured kernels through the device descriptors
+    batch_evolve(ga, steps, [p.dt / 2 for p in probs])
+    batch_evolve(gb, steps, [p.dt / 2 for p in probs])
+    for sa, sb in zip(ga, gb):
+        assert np.array_equal(sa.states()[1], sb.states()[1])
+    for s in ga + gb:
+        s.close()
