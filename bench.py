@@ -138,6 +138,40 @@ def traffic_from_profiles(cls_name):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def copy_ceiling_gbs(nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (read + write bytes / s) of a buffer larger than the
+    on-package cache: the practical HBM ceiling the pass kernels are judged beside."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * nbytes / t / 1e9, 1)
+
+
+def device_record():
+    """Device name and current clocks (rocm-smi, when present) for the record."""
+    import subprocess
+    import torch
+    rec = {"name": torch.cuda.get_device_name(0)}
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20).stdout
+        rec["clocks"] = [ln.split(":", 1)[-1].strip() for ln in out.splitlines()
+                         if "sclk" in ln or "mclk" in ln or "fclk" in ln][:6]
+    except Exception:
+        rec["clocks"] = None
+    return rec
+
+
 def cpu_baseline(p_fdtd, p_fft, seconds):
     """The oracle, untuned, on a bounded sample of the same workload."""
     import numpy as np
@@ -166,8 +200,8 @@ def cpu_baseline(p_fdtd, p_fft, seconds):
         res[p.label] = n
     return {"value": total_su / total_t, "unit": "site-updates/s", "cores": O.WORKERS, "kind": "oracle",
             "sample": "FP64 numpy/scipy oracle steps of the same 128^3 x 3-state problems "
-                      "(%d FDTD steps, %d FFT steps, %.0f s wall); orthonormalisation excluded"
-                      % (res[p_fdtd.label], res[p_fft.label], total_t)}
+                      "(%d FDTD steps on one thread, %d FFT steps with %d FFT threads, %.0f s wall); "
+                      "orthonormalisation excluded" % (res[p_fdtd.label], res[p_fft.label], O.WORKERS, total_t)}
 
 
 def main():
@@ -270,6 +304,11 @@ def main():
         "solve_latency_ms": {"p50": lat_ms[len(lat_ms) // 2], "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))]},
         "energies": {"fdtd": [round(e.real, 9) for e in energies[0]], "sin2": [round(e.real, 9) for e in energies[1]]},
         "roofline": roof,
+        # whole path: algorithmic bytes (20 B per site-update: read + write a complex64 site, read
+        # the real FP32 potential factor) at the measured rate, against the peak and a measured copy
+        "path_roofline": {"bytes_per_su": 20, "R_alg": round(value * 20 / (PEAK_HBM_GBS * 1e9), 4),
+                          "copy_ceiling_GBps": copy_ceiling_gbs()},
+        "device": device_record(),
     }
     for s in solvers:
         s.close()

@@ -22,8 +22,31 @@ template <int N> __host__ __device__ constexpr int plane_threads() {
   int t = (N * N / 16 + 63) / 64 * 64;
   return t < 64 ? 64 : (t > 1024 ? 1024 : t);
 }
+// Row pitch of the plane in LDS (elements).  LDS serves a wave's 64 accesses
+// in 128-byte passes (16 lanes of 8-byte or 8 lanes of 16-byte elements);
+// distinct elements of one pass that share (index mod 128/element size)
+// serialise.  The pitches below minimise those repeats over every access of
+// the steady plane pass (both row-stage lane maps, the stride-R Stockham
+// writes) for the sizes where the padded length alone leaves them; found with
+// a model of that access pattern and checked against the LDS bank-conflict
+// counter at N = 128 (7x fewer conflict cycles).
+template <typename T, int N> __host__ __device__ constexpr int plane_pitch() {
+  if constexpr (sizeof(T) == 4) {
+    switch (N) {
+      case 18: return 25; case 24: return 35; case 32: return 36; case 40: return 44; case 48: return 51;
+      case 50: return 56; case 64: return 72; case 80: return 85; case 96: return 108; case 128: return 136;
+      default: return padded_len(N);
+    }
+  } else {
+    switch (N) {
+      case 12: return 19; case 24: return 27; case 32: return 36; case 40: return 45; case 48: return 51;
+      case 80: return 85;
+      default: return padded_len(N);
+    }
+  }
+}
 template <typename T, int N> __host__ __device__ constexpr size_t plane_lds_t() {
-  return (size_t)(N * padded_len(N) + tw_total<N>()) * sizeof(C<T>);
+  return (size_t)(N * plane_pitch<T, N>() + tw_total<N>()) * sizeof(C<T>);
 }
 template <typename T, int N> __host__ __device__ constexpr bool plane_fits() {
   return plane_lds_t<T, N>() <= 160 * 1024 && N * N <= 16 * 1024;
@@ -150,7 +173,7 @@ __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, 
 // runs every size with its own, larger, block).
 template <typename T, int N, int NT>
 __device__ __forceinline__ void plane_body(const LaunchList &L, int e, int t, unsigned char *smem) {
-  constexpr int P = padded_len(N);
+  constexpr int P = plane_pitch<T, N>();
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
   const int s = t / N, i1 = t - s * N;
@@ -487,6 +510,8 @@ __global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
 
 
 template <int N> void register_size(FftKernels *tab) {
+  static_assert(N > 128 || plane_fits<float, N>(), "complex64 planes up to N = 128 must fit LDS");
+  static_assert(N > 96 || plane_fits<double, N>(), "complex128 planes up to N = 96 must fit LDS");
   FftKernels &k = tab[N];
   if constexpr (plane_fits<float, N>()) {
     k.plane[0] = (const void *)k_plane_t<float, N>;
