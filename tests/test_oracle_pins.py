@@ -230,6 +230,22 @@ def test_ho_fft_converges_to_tensor_products_of_1d_step_eigenvectors(kind):
         assert np.linalg.norm(r) < 1e-8
 
 
+def test_strang_bias_of_converged_energy_scales_as_dt4():
+    # the symmetric split step is exp(-dt H_eff) with H_eff = H + O(dt^2); its dominant
+    # eigenvector is off the lattice H's by O(dt^2), and the Rayleigh quotient is stationary at an
+    # eigenvector, so the converged <H> sits above E0 by O(dt^4): halving dt divides it by ~16
+    N, a, m = 16, 0.5, 1.0
+    K1, V1 = ho_1d(O.K_NR_SIN2, N, a, m, 0.1)
+    e0 = 3 * np.linalg.eigvalsh(K1 + V1)[0]
+    bias = []
+    for dt in (0.2, 0.1, 0.05):
+        p = S.Problem(N=N, a=a, m=m, kinetic=O.K_NR_SIN2, vkind=S.V_HARMONIC, vparams=(1.0,), k=1,
+                      dt=dt, steps=int(round(30 / dt)), seed=9)
+        bias.append(O.solve(p)["energies"][0].real - e0)
+    assert all(b > 0 for b in bias)                  # variational: never below the ground level
+    assert 15.0 < bias[0] / bias[1] < 17.0 and 15.5 < bias[1] / bias[2] < 16.5, bias
+
+
 def test_fdtd_ho_fixed_point_is_self_consistent_separable_problem():
     # fixed point psi' = mu psi of the A/B step solves (H_K + c V) psi = eps psi with
     # c = (1 + mu)/2 and mu = 1 - dt eps; H_K + c V is separable, so psi0 = w x w x w
