@@ -310,6 +310,19 @@ def main():
                           "copy_ceiling_GBps": copy_ceiling_gbs()},
         "device": device_record(),
     }
+    # outside the timed region: one solve of each form with the states handed over in host
+    # memory (FP64 upload, FP64 readback of states and energies): the PCIe-inclusive rate
+    for s in solvers:
+        s.enable_kernel_timing(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, p in zip(solvers, (p_fdtd, p_fft)):
+        s.set_states(init)
+        s.evolve(p.steps, p.dt)
+        s.states()
+    t_host = time.perf_counter() - t0
+    out["host_io"] = {"value": su_per_step / t_host, "unit": "site-updates/s",
+                      "note": "states uploaded from and read back to host memory (complex128) around each solve"}
     for s in solvers:
         s.close()
     if not args.no_cpu_baseline:

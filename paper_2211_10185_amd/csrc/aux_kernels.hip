@@ -251,14 +251,19 @@ __device__ __forceinline__ void stencil_tile(const C<T> *__restrict__ sp, C<T> *
 
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) k_stencil(const LaunchList L) {
-  const int e = find_entry(L, blockIdx.x);
+  // runs of 48 tiles per XCD: the states of a tile and its x2/x1 neighbours
+  // meet in one L2 (shorter runs lose that at 128^3, one run per XCD loses
+  // HBM-side balance at 256^3)
+  const int blk = xcd_block_chunked(blockIdx.x, gridDim.x, 48);
+  const int e = find_entry(L, blk);
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
   const int N = d.N;
   const int ntx = (N + ST_TX - 1) / ST_TX, nty = (N + ST_TY - 1) / ST_TY;
-  // states of one tile are adjacent in block order, so the potential (shared by
-  // all states) and the halo rows of neighbouring tiles are re-read from L2
-  int t = blockIdx.x - L.tile_start[e];
+  // states of one tile are adjacent in logical block order, so the potential
+  // (shared by all states) and the halo rows of neighbouring tiles are re-read
+  // from L2
+  int t = blk - L.tile_start[e];
   const int s = t % d.k; t /= d.k;
   const int bx = t % ntx; t /= ntx;
   const int by = t % nty; t /= nty;

@@ -110,6 +110,28 @@ struct LaunchList {
   int32_t aux[MAX_LAUNCH];         // per-entry extra (trace slot, ...)
 };
 
+// The dispatcher deals consecutive blocks of a grid to the chip's 8 XCDs in
+// turn, and each XCD has its own L2.  xcd_block maps the hardware block index
+// to a logical one so that every XCD receives one contiguous run of logical
+// blocks (a bijection on [0, G) for any G): tiles that share data (neighbours'
+// halos, one potential shared by several states) then meet in the same L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int q = G / NUM_XCD, r = G - q * NUM_XCD;
+  const int x = b % NUM_XCD, i = b / NUM_XCD;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+// Same in runs of `chunk` logical blocks: each group of NUM_XCD * chunk
+// hardware blocks gives every XCD `chunk` consecutive logical blocks; the
+// last, partial group falls back to xcd_block over its own range.
+__device__ __forceinline__ int xcd_block_chunked(int b, int G, int chunk) {
+  const int span = NUM_XCD * chunk;
+  const int full = (G / span) * span;
+  if (b >= full) return full + xcd_block(b - full, G - full);
+  const int g = b / span, w = b - g * span;
+  return g * span + (w % NUM_XCD) * chunk + w / NUM_XCD;
+}
+
 __device__ __forceinline__ int find_entry(const LaunchList &L, int blk) {
   int lo = 0, hi = L.n - 1;
   while (lo < hi) {
