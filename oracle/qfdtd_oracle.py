@@ -28,6 +28,10 @@ Readings of the paper that this oracle takes (the text is silent or ambiguous):
   h = exp(-dt V / 2).  H_K^(0) uses the legacy explicit form with the potential
   averaged over the step: psi <- A psi - B dt H_K^(0) psi,
   A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2).
+* The same legacy form with H_K^(0) swapped for an FFT kinetic term (the paper
+  changes only the kinetic operator of the legacy iteration) is the second
+  scheme, SCHEME_AB: psi <- A psi - B dt IFFT[T FFT[psi]].  It is stable for
+  dt <= 2 / max T (``ab_dt_bound``).
 * The printed H_K^(0) carries 1/(2A) * 1/A per neighbour difference; this
   oracle uses the standard 7-point Laplacian over A^2 (the paper states that
   H_K^(0) and H_K^(1,2) agree away from the walls, which needs that factor).
@@ -56,6 +60,7 @@ WORKERS = int(os.environ.get("QFDTD_ORACLE_THREADS", os.cpu_count() or 1))
 K_FDTD, K_NR_P2, K_NR_SIN2, K_REL = 0, 1, 2, 3
 V_GRID, V_HARMONIC, V_CORNELL, V_COULOMB, V_RADIAL_SPLINE = 0, 1, 2, 3, 4
 S_NONE, S_PLUS, S_MINUS, S_PK1, S_PK2, S_PK3 = 0, 1, 2, 3, 4, 5
+SCHEME_SPLIT, SCHEME_AB = 0, 1
 
 
 # --------------------------------------------------------------------------
@@ -181,6 +186,24 @@ def step_split(psi: np.ndarray, T: np.ndarray, V: np.ndarray, dt: float) -> np.n
     return h * ifft3(np.exp(-dt * T) * fft3(h * psi))
 
 
+def step_ab_fft(psi: np.ndarray, T: np.ndarray, V: np.ndarray, dt: float) -> np.ndarray:
+    """psi <- A psi - B dt H_K psi with H_K psi = IFFT[T FFT[psi]] (the legacy update, FFT kinetic term)."""
+    A = (1.0 - 0.5 * dt * V) / (1.0 + 0.5 * dt * V)
+    B = 1.0 / (1.0 + 0.5 * dt * V)
+    return A * psi - B * dt * ifft3(T * fft3(psi))
+
+
+def ab_dt_bound(kind: int, a: float, m: float) -> float:
+    """Largest stable dt of the A/B update: dt * max T <= 2 (max T at k = (pi, pi, pi))."""
+    if kind == K_FDTD or kind == K_NR_SIN2:
+        tmax = 6.0 / (m * a * a)
+    elif kind == K_NR_P2:
+        tmax = 3.0 * np.pi ** 2 / (2.0 * m * a * a)
+    else:
+        tmax = np.sqrt(12.0 / (a * a) + m * m) - m
+    return 2.0 / tmax
+
+
 def step_fdtd(psi: np.ndarray, V: np.ndarray, dt: float, a: float, m: float) -> np.ndarray:
     """psi <- A psi + B dt L_D psi / (2 M A^2), A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2)."""
     A = (1.0 - 0.5 * dt * V) / (1.0 + 0.5 * dt * V)
@@ -264,11 +287,12 @@ def project_and_orthonormalise(states, sectors, periodic):
 
 def evolve(states: List[np.ndarray], kind: int, a: float, m: float, V: np.ndarray,
            dt: float, steps: int, K: int, sectors: Sequence[int],
-           trace: Optional[list] = None) -> List[np.ndarray]:
+           trace: Optional[list] = None, scheme: int = SCHEME_SPLIT) -> List[np.ndarray]:
     """Run ``steps`` steps in chunks of K; project + orthonormalise after each chunk.
 
     ``states`` must already be projected and orthonormalised (see ``prepare``).
     If ``trace`` is a list, the energies after every chunk are appended to it.
+    ``scheme`` selects the step of the FFT kinetic terms (split operator or A/B).
     """
     periodic = kind != K_FDTD
     T = kinetic_symbol(kind, states[0].shape[-1], a, m) if periodic else None
@@ -276,7 +300,9 @@ def evolve(states: List[np.ndarray], kind: int, a: float, m: float, V: np.ndarra
     while done < steps:
         n = min(K, steps - done)
         for _ in range(n):
-            if periodic:
+            if periodic and scheme == SCHEME_AB:
+                states = [step_ab_fft(s, T, V, dt) for s in states]
+            elif periodic:
                 states = [step_split(s, T, V, dt) for s in states]
             else:
                 states = [step_fdtd(s, V, dt, a, m) for s in states]
@@ -308,7 +334,7 @@ def solve(p, steps: Optional[int] = None, init: Optional[np.ndarray] = None,
     periodic = p.kinetic != K_FDTD
     states = prepare(init, sectors, periodic)
     states = evolve(states, p.kinetic, p.a, p.m, V, p.dt, steps, p.measure_every, sectors,
-                    trace)
+                    trace, getattr(p, "scheme", SCHEME_SPLIT))
     E = energies(states, p.kinetic, p.a, p.m, V)
     return {"energies": E, "states": np.stack(states), "sectors": sectors}
 
@@ -327,7 +353,7 @@ def solve_until_converged(p, tol: float = 1e-8, max_steps: Optional[int] = None,
     E = None
     while done < max_steps:
         states = evolve(states, p.kinetic, p.a, p.m, V, p.dt, p.measure_every,
-                        p.measure_every, sectors)
+                        p.measure_every, sectors, None, getattr(p, "scheme", SCHEME_SPLIT))
         done += p.measure_every
         E = energies(states, p.kinetic, p.a, p.m, V, T)
         if prev is not None and abs(E[0] - prev) < tol:

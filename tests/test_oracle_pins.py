@@ -183,6 +183,37 @@ def test_fdtd_step_at_constant_potential_scales_sine_modes():
     np.testing.assert_allclose(got, mu * psi, atol=1e-13)
 
 
+@pytest.mark.parametrize("kind", [O.K_NR_P2, O.K_NR_SIN2, O.K_REL])
+def test_ab_fft_step_equals_dense_matrix(kind):
+    # legacy update with an FFT kinetic term: S = diag(A) - dt diag(B) K, complex V
+    N, a, m, dt = 6, 0.3, 1.2, 0.01
+    V = rnd((N, N, N), 15) * 3.0
+    psi = rnd((N, N, N), 16)
+    K = dense_kinetic(kind, N, a, m)
+    v = V.ravel()
+    A = (1 - dt * v / 2) / (1 + dt * v / 2)
+    B = 1 / (1 + dt * v / 2)
+    ref = (A * psi.ravel() - dt * B * (K @ psi.ravel())).reshape(N, N, N)
+    got = O.step_ab_fft(psi, O.kinetic_symbol(kind, N, a, m), V, dt)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("kind", [O.K_NR_P2, O.K_NR_SIN2, O.K_REL])
+def test_ab_dt_bound_is_where_the_nyquist_mode_flips(kind):
+    # V = 0: the checkerboard (k = (pi, pi, pi)) is the mode of largest T; at dt = 2 / max T the
+    # update maps it to exactly minus itself, and every other plane wave has |factor| < 1
+    N, a, m = 8, 0.4, 1.3
+    i = np.arange(N)
+    cb = (-1.0) ** (i[:, None, None] + i[None, :, None] + i[None, None, :]) + 0j
+    dt = O.ab_dt_bound(kind, a, m)
+    T = O.kinetic_symbol(kind, N, a, m)
+    out = O.step_ab_fft(cb, T, np.zeros((N, N, N)), dt)
+    np.testing.assert_allclose(out, -cb, atol=1e-12)
+    K = dense_kinetic(kind, N, a, m)
+    lam = np.linalg.eigvalsh((K + K.T) / 2)
+    assert np.all(np.abs(1 - dt * lam) <= 1 + 1e-12)
+
+
 # -------------------------------------------- separable harmonic oscillator
 
 def ho_1d(kind, N, a, m, dt):
@@ -268,6 +299,34 @@ def test_fdtd_ho_fixed_point_is_self_consistent_separable_problem():
     assert abs(res["energies"][0].real - e_ref) < 1e-11
     t0 = np.kron(np.kron(w, w), w)
     assert abs(abs(np.vdot(t0, res["states"][0].ravel())) - 1) < 1e-10
+
+
+@pytest.mark.parametrize("kind", [O.K_NR_P2, O.K_NR_SIN2])
+def test_ab_fft_ho_fixed_point_and_second_order_bias(kind):
+    # fixed point of the A/B update with a separable kinetic term: (K + c V) psi = eps psi,
+    # c = 1 - dt eps / 2, separable, so psi0 = w x w x w; its <H> exceeds H's E0 by O(dt^2)
+    N, a, m = 16, 0.5, 1.0
+    bias = []
+    for dt in (0.02, 0.01):
+        K1, V1 = ho_1d(kind, N, a, m, dt)
+        c = 1.0
+        for _ in range(300):
+            w_e, w_U = np.linalg.eigh(K1 + c * V1)
+            c_new = 1 - dt * 3 * w_e[0] / 2
+            if abs(c_new - c) < 1e-16:
+                break
+            c = c_new
+        w = w_U[:, 0]
+        e_ref = 3 * (w @ (K1 + V1) @ w)
+        p = S.Problem(N=N, a=a, m=m, kinetic=kind, vkind=S.V_HARMONIC, vparams=(1.0,), k=1,
+                      dt=dt, steps=int(round(40 / dt)), seed=8, scheme=S.SCHEME_AB)
+        res = O.solve(p)
+        E = res["energies"][0].real
+        assert abs(E - e_ref) < 1e-11
+        t0 = np.kron(np.kron(w, w), w)
+        assert abs(abs(np.vdot(t0, res["states"][0].ravel())) - 1) < 1e-10
+        bias.append(E - 3 * np.linalg.eigvalsh(K1 + V1)[0])
+    assert bias[0] > 0 and bias[1] > 0 and 3.8 < bias[0] / bias[1] < 4.2, bias
 
 
 def test_continuum_ho_levels_config1():
