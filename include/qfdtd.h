@@ -122,6 +122,16 @@ typedef struct {
                                      where an x2-x3 plane fits in LDS (schedule autotuning) */
 #define QFDTD_F_NO_GRAPH 4u       /* qfdtd_evolve: launch every chunk directly instead of capturing
                                      a chunk into a HIP graph once and replaying it */
+#define QFDTD_F_AB_SCHEME 8u      /* FFT kinds: step with the legacy update of H_K^(0) with the
+                                     FFT kinetic term swapped in (Sec. 2, the update the paper
+                                     keeps while changing H_K):  psi' = A psi - B dt H_K psi,
+                                     A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2), with
+                                     H_K psi = F^-1[T F[psi]].  Needs dt <= 2 / max T:
+                                     4 m a^2/(3 pi^2) (H_K^(1)), m a^2/3 (H_K^(2)),
+                                     2/(sqrt(12/a^2 + m^2) - m) (H_K^(3)); else
+                                     qfdtd_evolve returns QFDTD_E_UNSTABLE_DT.  Ignored for
+                                     H_K^(0), which always steps this way.  Default: the
+                                     symmetric split-operator step. */
 
 typedef struct qfdtd_ctx qfdtd_ctx;
 
@@ -145,7 +155,8 @@ qfdtd_status qfdtd_set_state_device(qfdtd_ctx *c, int32_t i, const void *psi_dev
 /* Advance all k states by `steps` imaginary-time steps of size dt (Sec. 2, eq.
  * (eq_iterat)), orthonormalising every K steps and after the last one.  Enqueued on
  * the stream; returns without waiting, except that a NaN/Inf found by an earlier
- * call is reported here.  QFDTD_E_UNSTABLE_DT for H_K^(0) when dt > m a^2 / 3. */
+ * call is reported here.  QFDTD_E_UNSTABLE_DT for H_K^(0) when dt > m a^2 / 3 and,
+ * with QFDTD_F_AB_SCHEME, for an FFT kind when dt exceeds its bound (see the flag). */
 qfdtd_status qfdtd_evolve(qfdtd_ctx *c, int64_t steps, double dt);
 
 /* Energies of states 0..k-1 (energies[2i], energies[2i+1] = Re, Im of E_i; H_K^(3)

@@ -41,6 +41,7 @@ class Options(ct.Structure):
 F_SINGLE_STREAM = 1
 F_ROWCOL = 2
 F_NO_GRAPH = 4
+F_AB_SCHEME = 8
 
 
 class QfdtdError(RuntimeError):

@@ -87,12 +87,13 @@ __global__ void k_potential(double *v64, int vcomplex, int N, double a, int kind
 // state-precision V (FDTD), and e^{-dt V/2}, e^{-dt V} (FFT kinds) from the FP64 table
 template <typename T>
 __global__ void k_dt_tables(const double *v64, int vcomplex, size_t N3, double dt, void *vtab, void *hfac,
-                            void *h2fac, T *ktab, const double *ksym64, int N, int kin) {
+                            void *h2fac, T *ktab, const double *ksym64, int N, int kin, int scheme) {
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g < (size_t)N && ktab) {
-    // separable symbols: e^{-dt t(k_j)}; relativistic: the lattice p^2 table itself
+    // separable symbols: e^{-dt t(k_j)} (split step) or t(k_j) (A/B update);
+    // relativistic: the lattice p^2 table itself
     const double ks = ksym64[g];
-    ktab[g] = (T)(kin == KIN_REL ? ks : exp(-dt * ks));
+    ktab[g] = (T)((kin == KIN_REL || scheme == SCHEME_AB) ? ks : exp(-dt * ks));
   }
   if (g >= N3) return;
   const double vr = vcomplex ? v64[2 * g] : v64[g];
@@ -675,15 +676,15 @@ void launch_potential(double *v64, int vcomplex, int N, double a, int kind, cons
                      p[1], p[2], knots, nk, add);
 }
 void launch_dt_tables(bool dbl, const double *v64, int vcomplex, int N, double dt, void *vtab, void *hfac, void *h2fac,
-                      void *ktab, const double *ksym64, int kin, hipStream_t st) {
+                      void *ktab, const double *ksym64, int kin, int scheme, hipStream_t st) {
   const size_t N3 = (size_t)N * N * N;
   const size_t n = N3 > (size_t)N ? N3 : (size_t)N;
   if (dbl)
     hipLaunchKernelGGL(k_dt_tables<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v64, vcomplex, N3, dt,
-                       vtab, hfac, h2fac, (double *)ktab, ksym64, N, kin);
+                       vtab, hfac, h2fac, (double *)ktab, ksym64, N, kin, scheme);
   else
     hipLaunchKernelGGL(k_dt_tables<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v64, vcomplex, N3, dt,
-                       vtab, hfac, h2fac, (float *)ktab, ksym64, N, kin);
+                       vtab, hfac, h2fac, (float *)ktab, ksym64, N, kin, scheme);
 }
 void launch_from64_slot(bool dbl, void *dst, const double2 *src, size_t n, hipStream_t st) {
   if (dbl) hipLaunchKernelGGL(k_from64_slot<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (double2 *)dst, src, n);

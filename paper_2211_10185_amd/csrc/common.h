@@ -67,8 +67,16 @@ enum : uint32_t {
   M_KIN = 32u,   // column pass: x e^{-dt T(k)}/N^3 between forward and inverse
   M_AXIS1 = 64u, // column pass along x1 (else x2)
   M_SWAP = 128u, // stencil: read alt, write psi (else read psi, write alt)
-  M_SCALE = 256u // column pass: x 1/N^3 after the last transform
+  M_SCALE = 256u, // column pass: x 1/N^3 after the last transform
+  // A/B update of the FFT kinetic terms (the legacy iteration with H_K^(1..3)):
+  M_COMB = 512u,  // real-space pass: input dt H_K psi (transformed) from alt; after the inverse,
+                  // psi' = A psi - B (dt H_K psi) with psi read from and psi' written to psi
+  M_ALT = 1024u   // transforms work on alt: column passes read/write alt, a real-space pass
+                  // without M_COMB reads psi and writes its forward transform to alt
 };
+
+// Step of the FFT kinetic terms
+enum { SCHEME_SPLIT = 0, SCHEME_AB = 1 };
 
 // Everything a kernel needs to know about one member (one solve).  Lives in
 // device memory; kernels index it through a launch list.
@@ -93,7 +101,7 @@ struct PassDesc {
   int32_t radix[MAX_STAGES];
   int32_t sector[MAX_STATES];
   int32_t nblk_red;       // reduction blocks per state sweep
-  int32_t pad0;
+  int32_t scheme;         // SCHEME_SPLIT or SCHEME_AB (FFT kinetic terms)
   double a, m, dt;
   double stencil_c;       // dt / (2 m a^2)
   double inv_n3;

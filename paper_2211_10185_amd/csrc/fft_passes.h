@@ -70,7 +70,8 @@ __device__ __forceinline__ C<T> vmul_t(C<T> v, const void *f, int vcomplex, size
   return cscale(v, ((const T *)f)[off]);
 }
 
-// e^{-dt T(k)} / N^3 at FFT indices (i1, i2, i3).
+// k-space factor at FFT indices (i1, i2, i3): e^{-dt T(k)} / N^3 for the split
+// step, dt T(k) / N^3 for the A/B update (the column pass then yields dt H_K psi).
 template <typename T>
 __device__ __forceinline__ T kin_factor_t(const PassDesc &d, int i1, int i2, int i3) {
   const T *kt = (const T *)d.ktab;
@@ -81,13 +82,36 @@ __device__ __forceinline__ T kin_factor_t(const PassDesc &d, int i1, int i2, int
       // single-instruction sqrt, reciprocal and 2^x (about 1 ulp each; the
       // factor's relative error stays far below the complex64 state's)
       const float tk = p2 * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(p2 + m * m) + m);
+      if (d.scheme == SCHEME_AB) return tk * (float)(d.dt * d.inv_n3);
       return __builtin_amdgcn_exp2f(-(float)d.dt * 1.4426950408889634f * tk) * (float)d.inv_n3;
     } else {
       const T tk = p2 / (sqrt(p2 + m * m) + m);   // sqrt(p^2 + m^2) - m without cancellation
+      if (d.scheme == SCHEME_AB) return tk * (T)(d.dt * d.inv_n3);
       return exp(-(T)d.dt * tk) * (T)d.inv_n3;
     }
   }
+  // separable terms: the table holds t(k_j) (A/B) or e^{-dt t(k_j)} (split)
+  if (d.scheme == SCHEME_AB) return (kt[i1] + kt[i2] + kt[i3]) * (T)(d.dt * d.inv_n3);
   return kt[i1] * kt[i2] * kt[i3] * (T)d.inv_n3;
+}
+
+// A/B update at one site: psi' = A psi - B x with x = dt H_K psi,
+// A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2) (complex when V is).
+template <typename T>
+__device__ __forceinline__ C<T> ab_combine(C<T> p, C<T> x, const PassDesc &d, size_t off) {
+  const T hdt = (T)(0.5 * d.dt);
+  if (d.vcomplex) {
+    const C<T> V = ((const C<T> *)d.vtab)[off];
+    const T dr = fmaT(hdt, V.x, (T)1), di = hdt * V.y;
+    const T den = (T)1 / fmaT(dr, dr, di * di);
+    const C<T> B = mkc<T>(dr * den, -di * den);
+    const C<T> A = cmul(mkc<T>(fmaT(-hdt, V.x, (T)1), -hdt * V.y), B);
+    return csub(cmul(A, p), cmul(B, x));
+  }
+  const T V = ((const T *)d.vtab)[off];
+  const T B = (T)1 / fmaT(hdt, V, (T)1);
+  const T A = fmaT(-hdt, V, (T)1) * B;
+  return mkc<T>(fmaT(A, p.x, -(B * x.x)), fmaT(A, p.y, -(B * x.y)));
 }
 
 template <typename T, int N, int NT>
@@ -168,6 +192,51 @@ __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, 
   }
 }
 
+// A/B update on one plane.  Chunk start (M_FWD | M_ALT): psi -> F3 F2 -> alt.
+// Steady (M_INV | M_COMB | M_FWD | M_ALT): alt -> F2^-1 F3^-1 gives dt H_K psi,
+// combined with psi into psi' (written to psi), then F3 F2 psi' -> alt.
+// Chunk end (M_INV | M_COMB): the same without the forward transform.
+template <typename T, int N, int NT, int P>
+__device__ __forceinline__ void plane_ab(C<T> *pl, const C<T> *tw, const PassDesc &d, uint32_t mode, int s, int i1) {
+  constexpr size_t N2 = (size_t)N * N;
+  const size_t base = ((size_t)s * N + i1) * N2;
+  C<T> *gp = (C<T> *)d.psi + base;
+  C<T> *ga = (C<T> *)d.alt + base;
+  const size_t voff = (size_t)i1 * N2;
+  const bool comb = (mode & M_COMB) != 0;
+  const C<T> *src = comb ? ga : gp;
+  for (int idx = threadIdx.x; idx < N * N; idx += NT) {
+    const int r = idx / N, c = idx - r * N;
+    pl[r * P + padn(c)] = src[idx];
+  }
+  __syncthreads();
+  using Rows = RowsGeo<N, P>;
+  using Cols = ColsGeo<N, P>;
+  if (mode & M_INV) {
+    fft_lines_t<T, N, true, Cols, NT>(pl, tw);
+    fft_lines_t<T, N, true, Rows, NT>(pl, tw);
+  }
+  if (comb) {
+    for (int idx = threadIdx.x; idx < N * N; idx += NT) {
+      const int r = idx / N, c = idx - r * N;
+      const int a = r * P + padn(c);
+      const C<T> o = ab_combine<T>(gp[idx], pl[a], d, voff + idx);
+      gp[idx] = o;
+      pl[a] = o;
+    }
+    __syncthreads();
+  }
+  if (mode & M_FWD) {
+    fft_lines_t<T, N, false, Rows, NT>(pl, tw);
+    fft_lines_t<T, N, false, Cols, NT>(pl, tw);
+    C<T> *dst = (mode & M_ALT) ? ga : gp;
+    for (int idx = threadIdx.x; idx < N * N; idx += NT) {
+      const int r = idx / N, c = idx - r * N;
+      dst[idx] = pl[r * P + padn(c)];
+    }
+  }
+}
+
 // Tile = one x2-x3 plane (state s, i1).  NT = threads of the block (the
 // plane kernel of a single size uses plane_threads<N>(); a multi-size kernel
 // runs every size with its own, larger, block).
@@ -183,6 +252,10 @@ __device__ __forceinline__ void plane_body(const LaunchList &L, int e, int t, un
   constexpr size_t N2 = (size_t)N * N;
   C<T> *g = (C<T> *)d.psi + ((size_t)s * N + i1) * N2;
   const size_t voff = (size_t)i1 * N2;
+  if (mode & (M_COMB | M_ALT)) {
+    plane_ab<T, N, NT, P>(pl, tw, d, mode, s, i1);
+    return;
+  }
   if constexpr (plan_of<N, false>().n >= 2) {
     if (mode == (M_INV | M_MID | M_FWD)) {
       __syncthreads();
@@ -286,6 +359,42 @@ __device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, c
   }
 }
 
+// A/B update on a row tile (modes as for plane_ab, transforms along x3 only).
+template <typename T, int N, int NT, int RB, int P>
+__device__ __forceinline__ void row_ab(C<T> *buf, const C<T> *tw, const PassDesc &d, uint32_t mode, long long row0,
+                                       int nrows, size_t voff0) {
+  constexpr size_t N3 = (size_t)N * N * N;
+  C<T> *gp = (C<T> *)d.psi + (size_t)row0 * N;
+  C<T> *ga = (C<T> *)d.alt + (size_t)row0 * N;
+  const bool comb = (mode & M_COMB) != 0;
+  const C<T> *src = comb ? ga : gp;
+  for (int idx = threadIdx.x; idx < RB * N; idx += NT) {
+    const int r = idx / N, c = idx - r * N;
+    buf[r * P + padn(c)] = r < nrows ? src[idx] : mkc<T>(0, 0);
+  }
+  __syncthreads();
+  using Rows = RowsGeo<RB, P>;
+  if (mode & M_INV) fft_lines_t<T, N, true, Rows, NT>(buf, tw);
+  if (comb) {
+    for (int idx = threadIdx.x; idx < nrows * N; idx += NT) {
+      const int r = idx / N, c = idx - r * N;
+      const int a = r * P + padn(c);
+      const C<T> o = ab_combine<T>(gp[idx], buf[a], d, (voff0 + idx) % N3);
+      gp[idx] = o;
+      buf[a] = o;
+    }
+    __syncthreads();
+  }
+  if (mode & M_FWD) {
+    fft_lines_t<T, N, false, Rows, NT>(buf, tw);
+    C<T> *dst = (mode & M_ALT) ? ga : gp;
+    for (int idx = threadIdx.x; idx < nrows * N; idx += NT) {
+      const int r = idx / N, c = idx - r * N;
+      dst[idx] = buf[r * P + padn(c)];
+    }
+  }
+}
+
 // Tile = RB consecutive x3 rows over all states (the last tile may be short).
 template <typename T, int N, int NT>
 __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsigned char *smem) {
@@ -303,6 +412,10 @@ __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsi
   C<T> *g = (C<T> *)d.psi + (size_t)row0 * N;
   // site offset of the tile's first row within its state; (voff0 + idx) % N^3 wraps at state boundaries
   const size_t voff0 = (size_t)(row0 % (long long)(N * N)) * N;
+  if (mode & (M_COMB | M_ALT)) {
+    row_ab<T, N, NT, RB, P>(buf, tw, d, mode, row0, nrows, voff0);
+    return;
+  }
   if constexpr (plan_of<N, false>().n >= 2) {
     if (mode == (M_INV | M_MID | M_FWD)) {
       __syncthreads();
@@ -457,7 +570,7 @@ __device__ __forceinline__ void col_body(const LaunchList &L, int e, int t, unsi
   C<T> *buf = (C<T> *)smem;
   C<T> *tw = buf + N * PC;
   load_tw<T, N, NT>(tw, d);
-  C<T> *g = (C<T> *)d.psi + (size_t)s * N * N * N + (size_t)o * OS + c0;
+  C<T> *g = (C<T> *)((mode & M_ALT) ? d.alt : d.psi) + (size_t)s * N * N * N + (size_t)o * OS + c0;
   using Geo = TileGeo<TC, PC>;
   if constexpr (plan_of<N, false>().n >= 2) {
     const int nc = (N - c0) < TC ? (N - c0) : TC;

@@ -34,7 +34,7 @@ void launch_tables(bool dbl, void *tw, double2 *tw64, double *ksym64, int N, int
 void launch_potential(double *v64, int vcomplex, int N, double a, int kind, const double *p, const double *knots, int nk,
                       const double2 *add, hipStream_t st);
 void launch_dt_tables(bool dbl, const double *v64, int vcomplex, int N, double dt, void *vtab, void *hfac, void *h2fac,
-                      void *ktab, const double *ksym64, int kin, hipStream_t st);
+                      void *ktab, const double *ksym64, int kin, int scheme, hipStream_t st);
 void launch_from64_slot(bool dbl, void *dst, const double2 *src, size_t n, hipStream_t st);
 void launch_to64_slot(bool dbl, double2 *dst, const void *src, size_t n, hipStream_t st);
 int ew_tiles_host(long long n);
@@ -178,6 +178,7 @@ struct qfdtd_ctx {
   double a = 0, m = 0;
   int sectors[MAX_STATES] = {0};
   bool any_parity = false, vcomplex = false, dbl = false, plane = false, plane64 = false;
+  int scheme = SCHEME_SPLIT;    // FFT kinds: split-operator step or A/B update
   hipStream_t st = nullptr;
   qfdtd_alloc_fn af = nullptr;
   qfdtd_free_fn ff = nullptr;
@@ -314,7 +315,10 @@ double entry_bytes(const Entry &e, Fam f) {
   const double fsz = (c->vcomplex ? 2.0 : 1.0) * (meas ? 8.0 : (double)c->rsz());
   switch (f) {
     case F_PLANE:
-    case F_ROW: return n * (2 * s + ((e.mode & (M_PRE | M_MID | M_POST)) ? fsz : 0.0));
+    case F_ROW:
+      // A/B combine: read alt and psi and V, write psi (and alt when the forward follows)
+      if (e.mode & M_COMB) return n * (3 * s + fsz + ((e.mode & M_FWD) ? s : 0.0));
+      return n * (2 * s + ((e.mode & (M_PRE | M_MID | M_POST)) ? fsz : 0.0));
     case F_COL: return n * 2 * s;
     case F_STENCIL: return n * (2 * s + fsz);
     default: return n * 2 * s;
@@ -548,10 +552,13 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
   for (size_t j = 0; j < ms.size(); ++j) {
     qfdtd_ctx *c = ms[j];
     if (!c->fft() || n[j] <= 0) continue;
-    if (c->plane) pl.push_back({c, 0, M_PRE | M_FWD, plane_tiles(c->N, c->k), 0});
+    // A/B update: the forward transform of psi goes to alt; psi stays for the combine
+    const uint32_t start = c->scheme == SCHEME_AB ? (uint32_t)(M_FWD | M_ALT) : (uint32_t)(M_PRE | M_FWD);
+    const uint32_t onalt = c->scheme == SCHEME_AB ? (uint32_t)M_ALT : 0u;
+    if (c->plane) pl.push_back({c, 0, start, plane_tiles(c->N, c->k), 0});
     else {
-      rw.push_back({c, 0, M_PRE | M_FWD, row_tiles(c->N, c->k), 0});
-      c2.push_back({c, 0, M_FWD, col_tiles(c->N, c->k, dbl), 0});
+      rw.push_back({c, 0, start, row_tiles(c->N, c->k), 0});
+      c2.push_back({c, 0, M_FWD | onalt, col_tiles(c->N, c->k, dbl), 0});
     }
   }
   QF_TRY(run_family(F_PLANE, pl, dbl));
@@ -569,13 +576,16 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
         continue;
       }
       const bool last = (s == n[j] - 1);
-      const uint32_t rs = last ? (M_INV | M_POST) : (M_INV | M_MID | M_FWD);
-      c1.push_back({c, 0, M_FWD | M_KIN | M_INV | M_AXIS1, col_tiles(c->N, c->k, dbl), 0});
+      const bool ab = c->scheme == SCHEME_AB;
+      const uint32_t onalt = ab ? (uint32_t)M_ALT : 0u;
+      uint32_t rs = last ? (M_INV | M_POST) : (M_INV | M_MID | M_FWD);
+      if (ab) rs = last ? (uint32_t)(M_INV | M_COMB) : (uint32_t)(M_INV | M_COMB | M_FWD | M_ALT);
+      c1.push_back({c, 0, M_FWD | M_KIN | M_INV | M_AXIS1 | onalt, col_tiles(c->N, c->k, dbl), 0});
       if (c->plane) pl.push_back({c, 0, rs, plane_tiles(c->N, c->k), 0});
       else {
-        c2.push_back({c, 0, M_INV, col_tiles(c->N, c->k, dbl), 0});
+        c2.push_back({c, 0, M_INV | onalt, col_tiles(c->N, c->k, dbl), 0});
         rw.push_back({c, 0, rs, row_tiles(c->N, c->k), 0});
-        if (!last) c2f.push_back({c, 0, M_FWD, col_tiles(c->N, c->k, dbl), 0});
+        if (!last) c2f.push_back({c, 0, M_FWD | onalt, col_tiles(c->N, c->k, dbl), 0});
       }
     }
     QF_TRY(run_family(F_COL, c1, dbl));
@@ -596,7 +606,7 @@ qfdtd_status upload_desc(qfdtd_ctx *c) {
 qfdtd_status set_dt(qfdtd_ctx *c, double dt) {
   if (dt == c->cur_dt) return QFDTD_OK;
   launch_dt_tables(c->dbl, c->v64, c->vcomplex ? 1 : 0, c->N, dt, c->vtab, c->hfac, c->h2fac, c->ktab, c->ksym64,
-                   c->kin, c->st);
+                   c->kin, c->scheme, c->st);
   QF_LAUNCHED(c);
   for (int w = 0; w < 4; ++w) {
     c->hd[w].dt = dt;
@@ -636,6 +646,16 @@ qfdtd_status validate_common(qfdtd_ctx *c) {
   return QFDTD_OK;
 }
 
+// Largest stable dt of the A/B update with an FFT kinetic term: dt max T <= 2,
+// max T at k = (pi, pi, pi) (eqs. HK1-HK3).
+double ab_dt_bound(int kin, double a, double m) {
+  double tmax;
+  if (kin == KIN_P2) tmax = 3.0 * M_PI * M_PI / (2.0 * m * a * a);
+  else if (kin == KIN_REL) tmax = std::sqrt(12.0 / (a * a) + m * m) - m;
+  else tmax = 6.0 / (m * a * a);
+  return 2.0 / tmax;
+}
+
 qfdtd_status batch_evolve_impl(qfdtd_ctx *const *members, int32_t n, const int64_t *steps, const double *dt) {
   std::vector<qfdtd_ctx *> ms;
   std::vector<int64_t> rem;
@@ -646,6 +666,8 @@ qfdtd_status batch_evolve_impl(qfdtd_ctx *const *members, int32_t n, const int64
     if (!(dt[j] > 0.0) || !std::isfinite(dt[j])) return fail(c, QFDTD_E_UNSTABLE_DT, "dt must be positive and finite");
     if (c->kin == KIN_FDTD && dt[j] > c->m * c->a * c->a / 3.0)
       return fail(c, QFDTD_E_UNSTABLE_DT, "H_K^(0) needs dt <= m a^2 / 3");
+    if (c->kin != KIN_FDTD && c->scheme == SCHEME_AB && dt[j] > ab_dt_bound(c->kin, c->a, c->m))
+      return fail(c, QFDTD_E_UNSTABLE_DT, "the A/B update needs dt <= 2 / max T(k)");
     if (steps[j] < 0) return fail(c, QFDTD_E_INVALID, "steps must be >= 0");
     if (j > 0 && (c->dbl != members[0]->dbl || c->st != members[0]->st))
       return fail(c, QFDTD_E_INVALID, "batch members need the same precision and stream");
@@ -867,6 +889,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     delete c;
     return fail(nullptr, QFDTD_E_UNSUPPORTED_N, "no transform kernels for this N");
   }
+  c->scheme = (c->fft() && (o.flags & QFDTD_F_AB_SCHEME)) ? SCHEME_AB : SCHEME_SPLIT;
   c->plane = c->fft() && g_fft[N].plane[c->dbl ? 1 : 0] != nullptr && !(o.flags & QFDTD_F_ROWCOL);
   c->plane64 = c->fft() && g_fft[N].plane[1] != nullptr;
   c->nblk_red = (int)((n3 + 2047) / 2048);
@@ -892,9 +915,10 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   const size_t cs = c->csz(), rs = c->rsz();
   const size_t fsz = (c->vcomplex ? 2 : 1) * rs;
   c->psi = dalloc(c, c->k * n3 * cs);
-  if (!c->fft() || c->any_parity) c->alt = dalloc(c, c->k * n3 * cs);
+  const bool ab = c->scheme == SCHEME_AB;
+  if (!c->fft() || c->any_parity || ab) c->alt = dalloc(c, c->k * n3 * cs);
   c->v64 = (double *)dalloc(c, n3 * 8 * (c->vcomplex ? 2 : 1));
-  if (!c->fft()) c->vtab = dalloc(c, n3 * fsz);
+  if (!c->fft() || ab) c->vtab = dalloc(c, n3 * fsz);
   else { c->hfac = dalloc(c, n3 * fsz); c->h2fac = dalloc(c, n3 * fsz); }
   c->ktab = dalloc(c, N * rs);
   c->tw = dalloc(c, N * cs);
@@ -907,7 +931,8 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   if (c->trace_on) c->trace = (double *)dalloc(c, (size_t)c->trace_cap * c->k * 2 * 8);
   c->d_desc = (PassDesc *)dalloc(c, sizeof(c->hd));
   bool ok = c->psi && c->v64 && c->ktab && c->tw && c->tw64 && c->ksym64 && c->scratch64 && c->partials && c->coef &&
-            c->energy && c->d_desc && (c->fft() || (c->alt && c->vtab)) && (!c->fft() || (c->hfac && c->h2fac)) &&
+            c->energy && c->d_desc && ((c->fft() && !ab) || (c->alt && c->vtab)) &&
+            (!c->fft() || ab || (c->hfac && c->h2fac)) &&
             (!c->any_parity || c->alt) && (!c->trace_on || c->trace);
   if (!ok) return bail(QFDTD_E_NOMEM, "device allocation failed");
   if (hipHostMalloc((void **)&c->h_status, sizeof(double)) != hipSuccess) return bail(QFDTD_E_NOMEM, "pinned allocation failed");
@@ -980,11 +1005,12 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     d.nst = make_plan(N, d.radix);
     for (int i = 0; i < c->k; ++i) d.sector[i] = c->sectors[i];
     d.nblk_red = c->nblk_red;
+    d.scheme = c->scheme;
     d.a = a; d.m = m; d.dt = 0.0; d.stencil_c = 0.0;
     d.inv_n3 = 1.0 / (double)n3;
   }
   // state groups for the two-stream schedule (plane schedule, k >= 2)
-  if (c->fft() && c->plane && c->k >= 2 && !(o.flags & QFDTD_F_SINGLE_STREAM)) {
+  if (c->fft() && c->plane && c->k >= 2 && !(o.flags & QFDTD_F_SINGLE_STREAM) && !ab) {
     c->ngroups = 2;
     c->gk[0] = (c->k + 1) / 2;
     c->gk[1] = c->k - c->gk[0];

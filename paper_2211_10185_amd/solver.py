@@ -79,7 +79,7 @@ class Solver:
                  n_states: int = 3, sectors: Optional[Sequence[int]] = None,
                  measure_every: int = 50, trace: bool = False, torch_alloc: bool = True,
                  single_stream: Optional[bool] = None, rowcol: Optional[bool] = None,
-                 graphs: bool = True):
+                 graphs: bool = True, scheme: int = 0):
         torch = _torch()
         self.N, self.a, self.m, self.kinetic = int(N), float(a), float(m), int(kinetic)
         self.precision, self.k = int(precision), int(n_states)
@@ -101,8 +101,10 @@ class Solver:
             single_stream = tuned["single_stream"] if single_stream is None else single_stream
             rowcol = tuned["rowcol"] if rowcol is None else rowcol
         self.schedule = {"single_stream": bool(single_stream), "rowcol": bool(rowcol)}
+        # scheme 1: the A/B update (psi' = A psi - B dt H_K psi) for the FFT kinetic terms
+        self.scheme = int(scheme)
         opt.flags = ((L.F_SINGLE_STREAM if single_stream else 0) | (L.F_ROWCOL if rowcol else 0)
-                     | (0 if graphs else L.F_NO_GRAPH))
+                     | (0 if graphs else L.F_NO_GRAPH) | (L.F_AB_SCHEME if self.scheme == 1 else 0))
         opt.hip_stream = ct.c_void_p(self.stream.cuda_stream)
         if self._alloc is not None:
             opt.dev_alloc = self._alloc.alloc
@@ -118,7 +120,8 @@ class Solver:
         grid = p.v_add_grid()
         s = cls(p.N, p.a, p.m, p.kinetic, p.vkind, p.vparams, knots=p.knots, grid=grid,
                 precision=p.precision if precision is None else precision, n_states=p.k,
-                sectors=p.sectors, measure_every=p.measure_every, trace=trace, **kw)
+                sectors=p.sectors, measure_every=p.measure_every, trace=trace,
+                **dict({"scheme": getattr(p, "scheme", 0)}, **kw))
         return s
 
     @property
