@@ -37,9 +37,10 @@ def parse():
     ap.add_argument("--timing-every", type=int, default=8, help="time one launch in this many")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="ho128", choices=["ho128", "batch64", "serve"],
-                    help="ho128: the headline 128^3 workload; batch64: 64 uneven Cornell solves in one "
-                         "batch; serve: Poisson-arrival serving trace")
+    ap.add_argument("--workload", default="ho128", choices=["ho128", "ab128", "batch64", "serve"],
+                    help="ho128: the headline 128^3 workload; ab128: the same problem with H_K^(2) "
+                         "stepped by the A/B update; batch64: 64 uneven Cornell solves in one batch; "
+                         "serve: Poisson-arrival serving trace")
     ap.add_argument("--requests", type=int, default=100, help="serve: number of requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--batch-steps", type=int, default=5000, help="batch64: imaginary-time steps")
@@ -78,6 +79,75 @@ def bench_batch(args):
                        "sites_total": sites, "sizes": sorted({p.N for p in members})},
             "solves_per_s": len(members) / el,
             "energy_min_max": [float(np.min(E.real[:, 0])), float(np.max(E.real[:, 0]))]}
+
+
+def roofline_of(solvers):
+    """Dominant pass class by total time (launch-attached HIP events), its algorithmic GB/s."""
+    stats = {}
+    for cls in (0, 1, 2, 3):
+        cnt, tot_ms, tot_b = 0, 0.0, 0.0
+        for s in solvers:
+            n, mean_ms, b = s.kernel_stats(cls)
+            cnt += n
+            tot_ms += n * mean_ms
+            tot_b += n * b
+        if cnt:
+            stats[cls] = (cnt, tot_ms / cnt, tot_b / cnt, tot_ms)
+    dom = max(stats, key=lambda c: stats[c][3])
+    cnt, mean_ms, bytes_per_launch, _ = stats[dom]
+    achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
+    return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                 "kernel": KERNEL_SYMBOLS[dom], "mean_launch_ms": round(mean_ms, 5),
+                 "algorithmic_bytes_per_launch": bytes_per_launch, "timed_launches": cnt,
+                 "by_class": {CLASS_NAMES[c]: {"mean_ms": round(v[1], 5),
+                                               "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1),
+                                               "share": round(v[3] / sum(x[3] for x in stats.values()), 3)}
+                              for c, v in stats.items()}}
+
+
+def bench_ab(args):
+    """The 128^3 harmonic problem with H_K^(2) stepped by the A/B update psi' = A psi - B dt H_K psi."""
+    import numpy as np
+    import torch
+    import synthetic as S
+    from paper_2211_10185_amd.solver import Solver
+    from paper_2211_10185_amd import _lib
+    p = S.config2(S.K_NR_SIN2)
+    p.scheme = S.SCHEME_AB
+    p.steps = args.imag_steps
+    N, k = p.N, p.k
+    init_dev = torch.from_numpy(p.init_states().astype(np.complex64)).to("cuda")
+    s = Solver.from_problem(p)
+
+    def solve():
+        for i in range(k):
+            s._c(_lib.lib.qfdtd_set_state_device(s.ctx, i, init_dev[i].data_ptr()))
+        s.evolve(p.steps, p.dt)
+        return s.energies()
+
+    for _ in range(args.warmup):
+        solve()
+    s.enable_kernel_timing(args.timing_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        E = solve()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    _, roof = roofline_of([s])
+    s.close()
+    value = k * N ** 3 * p.steps * args.steps / el
+    return {"metric": "lattice site-updates/s", "value": value, "unit": "site-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "harmonic oscillator 128^3, a=0.25, m=1, 3 states, dt=a^2/8, %d steps, "
+                                   "FFT H_K^(2) with the A/B update, complex64 states, FP64 reductions" % p.steps,
+                       "N": N, "states": k, "imag_steps": p.steps},
+            "energies": [round(e.real, 9) for e in E], "roofline": roof,
+            # pass model: column pass 16 B/SU + combine pass (alt, psi, V in; psi, alt out) 36 B/SU
+            "path_roofline": {"bytes_per_su": 20, "pass_bytes_per_su": 52,
+                              "R_alg": round(value * 20 / (PEAK_HBM_GBS * 1e9), 4)}}
 
 
 def bench_serve(args):
@@ -223,6 +293,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "ab128":
+        print(json.dumps(bench_ab(args)), flush=True)
         return
     dev = torch.device("cuda:0")
     p_fdtd = S.config2(S.K_FDTD)

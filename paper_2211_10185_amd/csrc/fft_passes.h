@@ -128,8 +128,14 @@ __device__ __forceinline__ void load_tw(C<T> *tw, const PassDesc &d) {
 template <typename T, bool VC> struct FacT { using type = T; };
 template <typename T> struct FacT<T, true> { using type = C<T>; };
 
-template <typename T, int N, int NT, int P, bool VC>
-__device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, const PassDesc &d, size_t voff) {
+//
+// AB: the steady pass of the A/B update instead: g is alt (holding the
+// transformed dt H_K psi), and the fused middle stage replaces the h^2
+// multiply by psi' = A psi - B (dt H_K psi), reading psi and writing psi' at
+// gp; the forward transform of psi' goes back to alt.
+template <typename T, int N, int NT, int P, bool VC, bool AB = false>
+__device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, const PassDesc &d, size_t voff,
+                                             C<T> *gp = nullptr) {
   using Rows = RowsGeo<N, P>;
   using Cols = ColsGeo<N, P>;
   constexpr RPlan PL = plan_of<N, false>();
@@ -139,14 +145,16 @@ __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, 
   constexpr int RMID = PL.r[M];
   using SMID = SG<Rows, N, RMID, NT>;
   using F = typename FacT<T, VC>::type;
-  F hq[SMID::CAPQ][RMID];
+  F hq[AB ? 1 : SMID::CAPQ][AB ? 1 : RMID];
+  if constexpr (!AB) {
 #pragma unroll
-  for (int q = 0; q < SMID::CAPQ; ++q) {
-    if (SMID::active(q)) {
-      int j, b;
-      SMID::jb(q, j, b);
+    for (int q = 0; q < SMID::CAPQ; ++q) {
+      if (SMID::active(q)) {
+        int j, b;
+        SMID::jb(q, j, b);
 #pragma unroll
-      for (int r = 0; r < RMID; ++r) hq[q][r] = ((const F *)d.h2fac)[voff + (size_t)b * N + j + r * SMID::NR];
+        for (int r = 0; r < RMID; ++r) hq[q][r] = ((const F *)d.h2fac)[voff + (size_t)b * N + j + r * SMID::NR];
+      }
     }
   }
   {
@@ -172,8 +180,17 @@ __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, 
         S::jb(q, j, b);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          if constexpr (VC) v[q][r] = cmul(v[q][r], hq[q][r]);
-          else v[q][r] = cscale(v[q][r], hq[q][r]);
+          if constexpr (AB) {
+            // the last inverse stage leaves element n = j + r N/R of line b in v[q][r]
+            const size_t o = (size_t)b * N + j + r * S::NR;
+            const C<T> y = ab_combine<T>(gp[o], v[q][r], d, voff + o);
+            gp[o] = y;
+            v[q][r] = y;
+          } else if constexpr (VC) {
+            v[q][r] = cmul(v[q][r], hq[q][r]);
+          } else {
+            v[q][r] = cscale(v[q][r], hq[q][r]);
+          }
         }
         Dft<R, false, C<T>>::run(v[q]);
       }
@@ -253,6 +270,14 @@ __device__ __forceinline__ void plane_body(const LaunchList &L, int e, int t, un
   C<T> *g = (C<T> *)d.psi + ((size_t)s * N + i1) * N2;
   const size_t voff = (size_t)i1 * N2;
   if (mode & (M_COMB | M_ALT)) {
+    if constexpr (plan_of<N, false>().n >= 2) {
+      if (mode == (M_INV | M_COMB | M_FWD | M_ALT)) {
+        __syncthreads();
+        C<T> *ga = (C<T> *)d.alt + ((size_t)s * N + i1) * N2;
+        plane_steady<T, N, NT, P, false, true>(pl, tw, ga, d, voff, g);
+        return;
+      }
+    }
     plane_ab<T, N, NT, P>(pl, tw, d, mode, s, i1);
     return;
   }
@@ -308,9 +333,9 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_plane_t(const LaunchList
 
 // Steady-state row pass (inverse x3 -> x h^2 -> forward x3): first stage from
 // HBM, last stage to HBM, middle stages fused around the potential factor.
-template <typename T, int N, int NT, int RB, int P>
+template <typename T, int N, int NT, int RB, int P, bool AB = false>
 __device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, const PassDesc &d, size_t voff0,
-                                           int nrows) {
+                                           int nrows, C<T> *gp = nullptr) {
   using Rows = RowsGeo<RB, P>;
   constexpr RPlan PL = plan_of<N, false>();
   constexpr int M = PL.n - 1;
@@ -338,8 +363,17 @@ __device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, c
         SS::jb(q, j, b);
         if (b < nrows) {
 #pragma unroll
-          for (int r = 0; r < R; ++r)
-            v[q][r] = vmul_t<T>(v[q][r], d.h2fac, d.vcomplex, (voff0 + (size_t)b * N + j + r * SS::NR) % N3);
+          for (int r = 0; r < R; ++r) {
+            if constexpr (AB) {
+              // A/B update (g is alt): psi' = A psi - B (dt H_K psi), psi read and written at gp
+              const size_t o = (size_t)b * N + j + r * SS::NR;
+              const C<T> y = ab_combine<T>(gp[o], v[q][r], d, (voff0 + o) % N3);
+              gp[o] = y;
+              v[q][r] = y;
+            } else {
+              v[q][r] = vmul_t<T>(v[q][r], d.h2fac, d.vcomplex, (voff0 + (size_t)b * N + j + r * SS::NR) % N3);
+            }
+          }
         }
         Dft<R, false, C<T>>::run(v[q]);
       }
@@ -413,6 +447,13 @@ __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsi
   // site offset of the tile's first row within its state; (voff0 + idx) % N^3 wraps at state boundaries
   const size_t voff0 = (size_t)(row0 % (long long)(N * N)) * N;
   if (mode & (M_COMB | M_ALT)) {
+    if constexpr (plan_of<N, false>().n >= 2) {
+      if (mode == (M_INV | M_COMB | M_FWD | M_ALT)) {
+        __syncthreads();
+        row_steady<T, N, NT, RB, P, true>(buf, tw, (C<T> *)d.alt + (size_t)row0 * N, d, voff0, nrows, g);
+        return;
+      }
+    }
     row_ab<T, N, NT, RB, P>(buf, tw, d, mode, row0, nrows, voff0);
     return;
   }
