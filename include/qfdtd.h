@@ -180,6 +180,13 @@ qfdtd_status qfdtd_energy_trace(qfdtd_ctx *c, double *out, int64_t cap, int64_t 
 qfdtd_status qfdtd_batch_evolve(qfdtd_ctx *const *members, int32_t n, const int64_t *steps,
                                 const double *dt);
 
+/* FP64 Gram matrix of the context's current states (Sec. 1: the overlaps that the
+ * orthogonal projection removes):  G_ij = <psi_i|psi_j> = sum_x conj(psi_i(x)) psi_j(x),
+ * reduced in FP64 in a fixed order.  The states are read as they are: as set (before any
+ * orthonormalisation) or as left by the last evolve.  G: host, [k][k][2] (re, im), row-major,
+ * caller-owned.  Synchronises the stream.  QFDTD_E_STATE if a state is unset. */
+qfdtd_status qfdtd_gram_matrix(qfdtd_ctx *c, double *G);
+
 /* Batched energy readout: energies[2*(j*kmax + i) + {0,1}] for member j, state i < k_j.
  * kmax = largest k among the members.  Synchronises the (common) stream. */
 qfdtd_status qfdtd_batch_energies(qfdtd_ctx *const *members, int32_t n, double *energies);

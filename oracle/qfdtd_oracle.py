@@ -177,6 +177,38 @@ def apply_hamiltonian(psi, kind, a, m, V, T=None):
 
 
 # --------------------------------------------------------------------------
+# closed forms of the continuum Coulomb problem (validation references, Sec. 3)
+# --------------------------------------------------------------------------
+
+def hydrogen_level(n: int, m: float, alpha: float) -> float:
+    """E_n = -m alpha^2 / (2 n^2) of H = p^2/(2m) - alpha/r."""
+    return -m * alpha * alpha / (2.0 * n * n)
+
+
+def hydrogen_state(name: str, N: int, a: float, m: float, alpha: float) -> np.ndarray:
+    """Continuum 1s, 2s or 2p_z (along x3) wavefunction sampled at the lattice sites, with the
+    continuum normalisation (a^3 sum |psi|^2 -> 1); Bohr radius a_B = 1/(m alpha)."""
+    aB = 1.0 / (m * alpha)
+    r = radius(N, a)
+    if name == "1s":
+        return np.exp(-r / aB) / np.sqrt(np.pi * aB ** 3)
+    if name == "2s":
+        return (2.0 - r / aB) * np.exp(-r / (2 * aB)) / np.sqrt(32 * np.pi * aB ** 3)
+    if name == "2p":
+        z = coords(N, a)[None, None, :]
+        return (z / aB) * np.exp(-r / (2 * aB)) / np.sqrt(32 * np.pi * aB ** 3)
+    raise ValueError(name)
+
+
+def hydrogen_1s_momentum(p: np.ndarray, m: float, alpha: float) -> np.ndarray:
+    """1s wavefunction in momentum space (wavenumber p, int |phi|^2 d^3p = 1):
+    phi(p) = 2 sqrt(2) a_B^{3/2} / (pi (1 + a_B^2 p^2)^2); the radial diagnostic of Sec. 3 is
+    y(p) = sqrt(4 pi) p phi(p)."""
+    aB = 1.0 / (m * alpha)
+    return 2.0 * np.sqrt(2.0) * aB ** 1.5 / (np.pi * (1.0 + (aB * p) ** 2) ** 2)
+
+
+# --------------------------------------------------------------------------
 # one imaginary-time step
 # --------------------------------------------------------------------------
 
@@ -321,7 +353,8 @@ def prepare(init: np.ndarray, sectors: Sequence[int], periodic: bool) -> List[np
 
 def problem_potential(p) -> np.ndarray:
     """V for a ``synthetic.Problem``."""
-    return potential(p.N, p.a, p.vkind, p.vparams, knots=p.knots, add_grid=p.v_add_grid())
+    return potential(p.N, p.a, p.vkind, p.vparams, knots=p.knots, grid=getattr(p, "grid", None),
+                     add_grid=p.v_add_grid())
 
 
 def solve(p, steps: Optional[int] = None, init: Optional[np.ndarray] = None,
@@ -360,3 +393,55 @@ def solve_until_converged(p, tol: float = 1e-8, max_steps: Optional[int] = None,
             break
         prev = E[0]
     return {"energies": E, "states": np.stack(states), "steps": done}
+
+
+# --------------------------------------------------------------------------
+# snapshot extraction of excited states (the legacy method, Sec. 1)
+# --------------------------------------------------------------------------
+
+def snapshot_run(p, steps: int, every: int, init: Optional[np.ndarray] = None):
+    """Evolve state 0 of ``p`` alone, normalised every ``every`` steps; the normalised state
+    after each chunk is a snapshot.  Returns (snapshots [n][N,N,N], taus [n])."""
+    V = problem_potential(p)
+    periodic = p.kinetic != K_FDTD
+    init = p.init_states() if init is None else init
+    sec = [p.sectors[0]] if p.sectors else [S_NONE]
+    st = prepare(init[:1], sec, periodic)
+    snaps, taus = [], []
+    done = 0
+    while done < steps:
+        n = min(every, steps - done)
+        st = evolve(st, p.kinetic, p.a, p.m, V, p.dt, n, n, sec, None, getattr(p, "scheme", SCHEME_SPLIT))
+        done += n
+        snaps.append(st[0].copy())
+        taus.append(done * p.dt)
+    return snaps, np.array(taus)
+
+
+def snapshot_energies(p, snaps: Sequence[np.ndarray], fixed: Sequence[np.ndarray]):
+    """Orthogonal projection of each snapshot against the orthonormal ``fixed`` states (in
+    order): returns (E(tau_j), r_j) with r_j the norm of the projected snapshot (the snapshots
+    have unit norm) and E(tau_j) the Rayleigh quotient of the projected snapshot."""
+    V = problem_potential(p)
+    E, r = [], []
+    for sj in snaps:
+        v = sj.copy()
+        for f in fixed:
+            v = v - inner(f, v) * f
+        nv = np.sqrt(inner(v, v).real)
+        r.append(nv)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            E.append(energies([v / nv], p.kinetic, p.a, p.m, V)[0] if nv > 0 else np.nan)
+    return np.array(E), np.array(r)
+
+
+def stationary_point(E: np.ndarray, r: np.ndarray, floor: float):
+    """Where E(tau_j) stops improving: its minimum (real part) over the snapshots whose
+    projected norm r_j exceeds ``floor``.  The Rayleigh quotient of a projected snapshot falls
+    while the higher levels decay; once r_j nears the rounding of the projection the remainder is
+    noise.  Returns (index, value)."""
+    e = np.real(np.asarray(E)).astype(np.float64)
+    ok = np.isfinite(e) & (np.asarray(r) > floor)
+    e = np.where(ok, e, np.inf)
+    j = int(np.argmin(e))
+    return j, float(e[j])

@@ -74,6 +74,7 @@ _sig = {
     "qfdtd_energy_trace": (ct.c_int, [P, DP, ct.c_int64, ct.POINTER(ct.c_int64)]),
     "qfdtd_batch_evolve": (ct.c_int, [ct.POINTER(P), ct.c_int32, ct.POINTER(ct.c_int64), DP]),
     "qfdtd_batch_energies": (ct.c_int, [ct.POINTER(P), ct.c_int32, DP]),
+    "qfdtd_gram_matrix": (ct.c_int, [P, DP]),
     "qfdtd_footprint": (ct.c_size_t, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32]),
     "qfdtd_enable_kernel_timing": (ct.c_int, [P, ct.c_int32]),
     "qfdtd_kernel_stats": (ct.c_int, [P, ct.c_int32, ct.POINTER(ct.c_int64), DP, DP]),

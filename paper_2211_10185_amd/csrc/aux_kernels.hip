@@ -412,6 +412,14 @@ __device__ double block_sum_column(const double *part, int nb, int q) {
   return r;
 }
 
+// The Gram matrix itself: fixed-order sums of the partials into out[nq] (one block).
+__global__ void __launch_bounds__(RED_THREADS) k_gram_sum(const double *partials, int nb, int nq, double *out) {
+  for (int q = 0; q < nq; ++q) {
+    const double v = block_sum_column(partials, nb, q);
+    if (threadIdx.x == 0) out[q] = v;
+  }
+}
+
 // Sum the partials (fixed order), Cholesky G = R^H R per sector, coef = R^{-1}.
 __global__ void __launch_bounds__(RED_THREADS) k_gram_finalize(const LaunchList L) {
   const int e = blockIdx.x;
@@ -747,6 +755,9 @@ void launch_kin_partials(const LaunchList &L, int total, int KS, hipStream_t st)
 #define K_(K) hipLaunchKernelGGL((k_kin_partials<K>), dim3(total), dim3(RED_THREADS), 0, st, L);
   QF_KS_SWITCH(KS, K_)
 #undef K_
+}
+void launch_gram_sum(const double *partials, int nb, int nq, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gram_sum, dim3(1), dim3(RED_THREADS), 0, st, partials, nb, nq, out);
 }
 void launch_gram_finalize(const LaunchList &L, hipStream_t st) {
   hipLaunchKernelGGL(k_gram_finalize, dim3(L.n), dim3(RED_THREADS), 0, st, L);

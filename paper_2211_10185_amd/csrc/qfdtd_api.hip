@@ -47,6 +47,7 @@ void launch_apply(const LaunchList &L, int total, int KS, bool dbl, hipStream_t 
 void launch_energy_partials(const LaunchList &L, int total, int KS, bool dbl, hipStream_t st);
 void launch_kin_partials(const LaunchList &L, int total, int KS, hipStream_t st);
 void launch_gram_finalize(const LaunchList &L, hipStream_t st);
+void launch_gram_sum(const double *partials, int nb, int nq, double *out, hipStream_t st);
 void launch_energy_finalize(const LaunchList &L, hipStream_t st);
 }  // namespace qf
 
@@ -1133,6 +1134,31 @@ qfdtd_status qfdtd_states_device(qfdtd_ctx *c, int32_t k, double *en, void *psi_
     std::memcpy(en, e.data(), (size_t)2 * k * 8);
   }
   if (psi_dev) QF_HIP(c, hipMemcpyAsync(psi_dev, c->psi, (size_t)k * c->n3() * c->csz(), hipMemcpyDeviceToDevice, c->st));
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_gram_matrix(qfdtd_ctx *c, double *G) {
+  if (!c || !G) return fail(c, QFDTD_E_INVALID, "NULL argument");
+  QF_TRY(check_status(c, false));
+  QF_TRY(validate_common(c));
+  std::vector<Entry> gram{{c, 0, c->cur ? (uint32_t)M_SWAP : 0u, c->nblk_red, 0}};
+  QF_TRY(run_by_k(F_GRAM, gram, c->dbl));
+  // the orthonormalisation coefficients are rewritten before every use, so their buffer
+  // holds the sums here
+  const int NP = c->k * (c->k + 1) / 2;
+  launch_gram_sum(c->partials, c->nblk_red, 2 * NP, c->coef, c->st);
+  QF_LAUNCHED(c);
+  std::vector<double> g(2 * NP);
+  QF_HIP(c, hipMemcpyAsync(g.data(), c->coef, (size_t)2 * NP * 8, hipMemcpyDeviceToHost, c->st));
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  int p = 0;
+  for (int i = 0; i < c->k; ++i)
+    for (int j = i; j < c->k; ++j, ++p) {
+      G[2 * (i * c->k + j)] = g[2 * p];
+      G[2 * (i * c->k + j) + 1] = g[2 * p + 1];
+      G[2 * (j * c->k + i)] = g[2 * p];
+      G[2 * (j * c->k + i) + 1] = -g[2 * p + 1];
+    }
   return QFDTD_OK;
 }
 

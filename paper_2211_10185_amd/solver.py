@@ -117,7 +117,7 @@ class Solver:
     @classmethod
     def from_problem(cls, p, precision: Optional[int] = None, trace: bool = False, **kw):
         """Build from a ``synthetic.Problem`` (potential evaluated on the device)."""
-        grid = p.v_add_grid()
+        grid = p.abi_grid()
         s = cls(p.N, p.a, p.m, p.kinetic, p.vkind, p.vparams, knots=p.knots, grid=grid,
                 precision=p.precision if precision is None else precision, n_states=p.k,
                 sectors=p.sectors, measure_every=p.measure_every, trace=trace,
@@ -155,6 +155,20 @@ class Solver:
 
     def energies(self):
         return self.states(with_psi=False)
+
+    def gram(self) -> np.ndarray:
+        """FP64 Gram matrix <psi_i|psi_j> of the current states (k x k, complex)."""
+        g = np.zeros(2 * self.k * self.k, dtype=np.float64)
+        self._c(L.lib.qfdtd_gram_matrix(self._ctx, g.ctypes.data_as(ct.POINTER(ct.c_double))))
+        return (g[0::2] + 1j * g[1::2]).reshape(self.k, self.k)
+
+    def set_state_device(self, i: int, t):
+        """State i from a contiguous device tensor in the solver's precision (stream-ordered)."""
+        torch = _torch()
+        want = torch.complex64 if self.precision == C64 else torch.complex128
+        if t.dtype != want or not t.is_cuda or not t.is_contiguous() or t.numel() != self.N ** 3:
+            raise ValueError("need a contiguous CUDA tensor of N^3 %s elements" % want)
+        self._c(L.lib.qfdtd_set_state_device(self._ctx, int(i), ct.c_void_p(t.data_ptr())))
 
     def energy_trace(self):
         n = ct.c_int64()

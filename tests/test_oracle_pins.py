@@ -572,3 +572,106 @@ def test_relativistic_term_tends_to_nonrelativistic_limit():
         rel.append(np.linalg.norm(h3 - h2) / np.linalg.norm(h2))
     assert rel[0] > rel[1] > rel[2]
     assert 3.0 < rel[0] / rel[1] < 5.0     # O(p^2 / M^2)
+
+
+# ----------------------------------------------- Coulomb validation references
+
+def _radial(name, r, aB):
+    if name == "1s":
+        return np.exp(-r / aB) / np.sqrt(np.pi * aB ** 3), 0
+    if name == "2s":
+        return (2 - r / aB) * np.exp(-r / (2 * aB)) / np.sqrt(32 * np.pi * aB ** 3), 0
+    return (r / aB) * np.exp(-r / (2 * aB)) / np.sqrt(32 * np.pi * aB ** 3), 1   # times cos(theta)
+
+
+def test_hydrogen_closed_forms_solve_the_radial_equation():
+    from scipy import integrate
+    m, alpha = 1.52, 1.1
+    aB = 1 / (m * alpha)
+    # the oracle's sampled states agree with the radial forms on the lattice
+    N, a = 16, 0.1
+    r = O.radius(N, a)
+    z = O.coords(N, a)[None, None, :]
+    for name in ("1s", "2s", "2p"):
+        R, l = _radial(name, r, aB)
+        ref = R * (z / np.where(r > 0, r, 1) if l else 1)
+        np.testing.assert_allclose(O.hydrogen_state(name, N, a, m, alpha), ref, rtol=1e-13, atol=1e-300)
+    # normalisation (angular factor 4 pi, or 4 pi / 3 for cos^2) and 1s/2s orthogonality
+    for name in ("1s", "2s", "2p"):
+        R = lambda x, nm=name: _radial(nm, x, aB)[0]
+        ang = 4 * np.pi / 3 if name == "2p" else 4 * np.pi
+        val = integrate.quad(lambda x: R(x) ** 2 * x * x, 0, np.inf)[0] * ang
+        assert abs(val - 1) < 1e-10, (name, val)
+    ov = integrate.quad(lambda x: _radial("1s", x, aB)[0] * _radial("2s", x, aB)[0] * x * x, 0, np.inf)[0]
+    assert abs(ov) < 1e-10
+    # -(1/2m)(R'' + 2R'/r - l(l+1)R/r^2) - alpha R / r = E_n R, derivatives by central differences
+    for name, n in (("1s", 1), ("2s", 2), ("2p", 2)):
+        E = O.hydrogen_level(n, m, alpha)
+        for x in (0.3 * aB, 1.0 * aB, 2.7 * aB, 6.0 * aB):
+            h = 1e-4 * aB
+            R = lambda y: _radial(name, y, aB)[0]
+            l = _radial(name, x, aB)[1]
+            d1 = (R(x + h) - R(x - h)) / (2 * h)
+            d2 = (R(x + h) - 2 * R(x) + R(x - h)) / (h * h)
+            lhs = -(d2 + 2 * d1 / x - l * (l + 1) * R(x) / x ** 2) / (2 * m) - alpha * R(x) / x
+            assert abs(lhs - E * R(x)) < 1e-5 * abs(E) * np.abs(_radial(name, np.array([0.5 * aB]), aB)[0][0])
+
+
+def test_hydrogen_1s_momentum_form_is_the_fourier_transform():
+    from scipy import integrate
+    m, alpha = 1.52, 0.9
+    aB = 1 / (m * alpha)
+    for p in (0.05, 0.7, 2.0, 6.0):
+        g = lambda r: r * np.sin(p * r) * np.exp(-r / aB) / np.sqrt(np.pi * aB ** 3)
+        ft = (2 * np.pi) ** -1.5 * 4 * np.pi / p * integrate.quad(g, 0, np.inf, limit=400)[0]
+        assert abs(ft - O.hydrogen_1s_momentum(np.array([p]), m, alpha)[0]) < 1e-9 * aB ** 1.5
+    # normalised in momentum space
+    val = integrate.quad(lambda p: O.hydrogen_1s_momentum(np.array([p]), m, alpha)[0] ** 2 * 4 * np.pi * p * p,
+                         0, np.inf)[0]
+    assert abs(val - 1) < 1e-9
+
+
+# ------------------------------------------------------- snapshot extraction
+
+def aniso_levels(N, a, m, omegas):
+    # the three lowest levels of the separable anisotropic oscillator (sin^2 kinetic term)
+    eps = [np.linalg.eigvalsh(-d2_periodic(N) / (2 * m * a * a) + np.diag(0.5 * w * w * O.coords(N, a) ** 2))
+           for w in omegas]
+    base = sum(e[0] for e in eps)
+    ex = sorted([base + e[1] - e[0] for e in eps] + [base + e[2] - e[0] for e in eps])
+    return base, ex[0], ex[1]
+
+
+def test_snapshot_extraction_reaches_exact_levels_and_fails_in_fp32():
+    # anisotropic HO (omega = 1, 1.3, 1.7: non-degenerate lowest levels).  The stationary point
+    # of E1(tau) from snapshots projected against the final state is the first excited level; a
+    # second projection (against the final state and the first excited state found) gives the
+    # second.  The best reachable error is set by the crossover of the decaying next-level
+    # contamination, e^{-2 (E2 - E1) tau}, and the excited component sinking into rounding,
+    # e^{-(E1 - E0) tau} vs. the precision: about 4e-7 in FP64, but only about 5e-3 once the
+    # snapshots are rounded to complex64 (the failure mode of the legacy extraction in single
+    # precision; the block method reaches the complex64 budget of 1e-5).
+    N, a, m = 16, 0.5, 1.0
+    om = (1.0, 1.3, 1.7)
+    dt = a * a / 8
+    e0, e1, e2 = aniso_levels(N, a, m, om)
+    p = S.Problem(N=N, a=a, m=m, kinetic=O.K_NR_SIN2, vkind=S.V_GRID, k=1, dt=dt, steps=0, seed=21,
+                  grid=S.anisotropic_ho_grid(N, a, om))
+    snaps, taus = O.snapshot_run(p, 4000, 50)
+    phi0 = snaps[-1]
+    V = O.problem_potential(p)
+    assert abs(O.energies([phi0], p.kinetic, a, m, V)[0].real - e0) < 1e-7
+    floor64, floor32 = 1e3 * 2.2e-16, 1e3 * 1.2e-7      # projections below this are rounding
+    E1, r1 = O.snapshot_energies(p, snaps, [phi0])
+    j1, v1 = O.stationary_point(E1, r1, floor64)
+    assert 0 < v1 - e1 < 2e-6, (v1, e1)
+    w = snaps[j1] - O.inner(phi0, snaps[j1]) * phi0
+    w = w / np.sqrt(O.inner(w, w).real)
+    E2, r2 = O.snapshot_energies(p, snaps, [phi0, w])
+    j2, v2 = O.stationary_point(E2, r2, floor64)
+    assert 0 < v2 - e2 < 1e-3, (v2, e2)
+    s32 = [x.astype(np.complex64).astype(np.complex128) for x in snaps]
+    E1f, r1f = O.snapshot_energies(p, s32, [s32[-1]])
+    j1f, v1f = O.stationary_point(E1f, r1f, floor32)
+    assert 1e-4 < v1f - e1 < 2e-2, v1f - e1
+    assert taus[j1f] < taus[j1]
