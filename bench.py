@@ -37,9 +37,10 @@ def parse():
     ap.add_argument("--timing-every", type=int, default=8, help="time one launch in this many")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="ho128", choices=["ho128", "ab128", "batch64", "serve"],
+    ap.add_argument("--workload", default="ho128", choices=["ho128", "ab128", "coulomb", "batch64", "serve"],
                     help="ho128: the headline 128^3 workload; ab128: the same problem with H_K^(2) "
-                         "stepped by the A/B update; batch64: 64 uneven Cornell solves in one batch; "
+                         "stepped by the A/B update; coulomb: the Coulomb validation workload at 128^3; "
+                         "batch64: 64 uneven Cornell solves in one batch; "
                          "serve: Poisson-arrival serving trace")
     ap.add_argument("--requests", type=int, default=100, help="serve: number of requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
@@ -106,16 +107,12 @@ def roofline_of(solvers):
                               for c, v in stats.items()}}
 
 
-def bench_ab(args):
-    """The 128^3 harmonic problem with H_K^(2) stepped by the A/B update psi' = A psi - B dt H_K psi."""
+def bench_problem(args, p, workload, extra=None):
+    """Site-updates/s of one solve of ``p`` (states resident on the device before timing)."""
     import numpy as np
     import torch
-    import synthetic as S
     from paper_2211_10185_amd.solver import Solver
     from paper_2211_10185_amd import _lib
-    p = S.config2(S.K_NR_SIN2)
-    p.scheme = S.SCHEME_AB
-    p.steps = args.imag_steps
     N, k = p.N, p.k
     init_dev = torch.from_numpy(p.init_states().astype(np.complex64)).to("cuda")
     s = Solver.from_problem(p)
@@ -138,16 +135,40 @@ def bench_ab(args):
     _, roof = roofline_of([s])
     s.close()
     value = k * N ** 3 * p.steps * args.steps / el
-    return {"metric": "lattice site-updates/s", "value": value, "unit": "site-updates/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": "harmonic oscillator 128^3, a=0.25, m=1, 3 states, dt=a^2/8, %d steps, "
-                                   "FFT H_K^(2) with the A/B update, complex64 states, FP64 reductions" % p.steps,
-                       "N": N, "states": k, "imag_steps": p.steps},
-            "energies": [round(e.real, 9) for e in E], "roofline": roof,
-            # pass model: column pass 16 B/SU + combine pass (alt, psi, V in; psi, alt out) 36 B/SU
-            "path_roofline": {"bytes_per_su": 20, "pass_bytes_per_su": 52,
-                              "R_alg": round(value * 20 / (PEAK_HBM_GBS * 1e9), 4)}}
+    out = {"metric": "lattice site-updates/s", "value": value, "unit": "site-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": workload, "N": N, "states": k, "imag_steps": p.steps},
+           "energies": [round(e.real, 9) for e in E], "roofline": roof}
+    out.update(extra or {})
+    return out
+
+
+def bench_ab(args):
+    """The 128^3 harmonic problem with H_K^(2) stepped by the A/B update psi' = A psi - B dt H_K psi."""
+    import synthetic as S
+    p = S.config2(S.K_NR_SIN2)
+    p.scheme = S.SCHEME_AB
+    p.steps = args.imag_steps
+    out = bench_problem(args, p, "harmonic oscillator 128^3, a=0.25, m=1, 3 states, dt=a^2/8, %d steps, "
+                                 "FFT H_K^(2) with the A/B update, complex64 states, FP64 reductions" % p.steps)
+    # pass model: column pass 16 B/SU + combine pass (alt, psi, V in; psi, alt out) 36 B/SU
+    out["path_roofline"] = {"bytes_per_su": 20, "pass_bytes_per_su": 52,
+                            "R_alg": round(out["value"] * 20 / (PEAK_HBM_GBS * 1e9), 4)}
+    return out
+
+
+def bench_coulomb(args):
+    """Coulomb validation workload: 128^3, a = 0.12 fm, m = 0.3 GeV, alpha = 1, H_K^(2), 1s/2s/2p_z
+    in the sectors (P+, P+, P^-_{p3}), run to tau = 80 fm; energies against -m alpha^2/(2 n^2)."""
+    import oracle as O
+    import synthetic as S
+    p = S.coulomb_problem(S.K_NR_SIN2, N=128, a=0.12, alpha=1.0)
+    out = bench_problem(args, p, "Coulomb 128^3, a=0.12 fm, m=0.3 GeV, alpha=1, H_K^(2), sectors P+,P+,P-_p3, "
+                                 "%d steps (tau=80 fm), complex64 states, FP64 reductions" % p.steps)
+    th = [O.hydrogen_level(n, p.m, 1.0) for n in (1, 2, 2)]
+    out["hydrogen_rel_error"] = [round((e - t) / abs(t), 5) for e, t in zip(out["energies"], th)]
+    return out
 
 
 def bench_serve(args):
@@ -296,6 +317,9 @@ def main():
         return
     if args.workload == "ab128":
         print(json.dumps(bench_ab(args)), flush=True)
+        return
+    if args.workload == "coulomb":
+        print(json.dumps(bench_coulomb(args)), flush=True)
         return
     dev = torch.device("cuda:0")
     p_fdtd = S.config2(S.K_FDTD)
