@@ -199,7 +199,9 @@ size_t qfdtd_footprint(int32_t N, int32_t kinetic, int32_t precision, int32_t n_
  * qfdtd_kernel_stats returns, for class `cls` (0 plane, 1 row, 2 column, 3 stencil,
  * 4 measurement), the number of timed launches, their mean duration in ms and the
  * algorithmic bytes one launch of that class moves (read once + written once).
- * Synchronises the stream. */
+ * While timing is enabled the states of an FFT solve are not split over two internal
+ * streams, so timed launches never overlap other kernels of the context.  every <= 0
+ * disables timing.  Synchronises the stream. */
 qfdtd_status qfdtd_enable_kernel_timing(qfdtd_ctx *c, int32_t every);
 qfdtd_status qfdtd_kernel_stats(qfdtd_ctx *c, int32_t cls, int64_t *count, double *mean_ms,
                                 double *bytes_per_launch);

@@ -544,7 +544,10 @@ qfdtd_status run_chunk_grouped(qfdtd_ctx *c, int n) {
 
 qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
   if (ms.empty()) return QFDTD_OK;
-  if (ms.size() == 1 && ms[0]->ngroups == 2 && n[0] > 0) return run_chunk_grouped(ms[0], n[0]);
+  // while launches are timed the state groups run on one stream, so that every timed launch
+  // has the device to itself (as under a profiler) and its duration is the kernel's own
+  if (ms.size() == 1 && ms[0]->ngroups == 2 && n[0] > 0 && ms[0]->timer.every <= 0)
+    return run_chunk_grouped(ms[0], n[0]);
   const bool dbl = ms[0]->dbl;
   int maxn = 0;
   for (int v : n) maxn = v > maxn ? v : maxn;
