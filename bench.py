@@ -209,12 +209,16 @@ def bench_serve(args):
             "converged": int(sum(r.converged for r in out32["results"]))}
 
 
+KERNEL_SOURCES = ("common.h", "fft_core.h", "fft_passes.h", "fft_inst.hip", "aux_kernels.hip")
+
+
 def source_hash():
+    """Hash of the device-kernel sources (the host library is left out: its changes do not move
+    the profiled traffic)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2211_10185_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -235,7 +239,7 @@ def traffic_from_profiles(cls_name):
 
 def copy_ceiling_gbs(nbytes=1 << 30, reps=5):
     """Device-to-device copy rate (read + write bytes / s) of a buffer larger than the
-    on-package cache: the practical HBM ceiling the pass kernels are judged beside."""
+    on-package cache: the practical HBM ceiling to set the pass kernels against."""
     import torch
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)

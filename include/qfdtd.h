@@ -194,6 +194,22 @@ qfdtd_status qfdtd_batch_energies(qfdtd_ctx *const *members, int32_t n, double *
 /* Device bytes the context for this problem would hold (for admission control). */
 size_t qfdtd_footprint(int32_t N, int32_t kinetic, int32_t precision, int32_t n_states);
 
+/* Complex potentials from ASCII files of numbers (Sec. 1: arbitrary complex potentials
+ * loaded from ASCII files), for qfdtd_potential.grid with kind QFDTD_V_GRID.  Host only
+ * (no device work).  A record is a line; '#' starts a comment; fields are separated by
+ * blanks, tabs or commas; every record has the same number of fields:
+ *   1: re    2: re im               N^3 records in C order (x3 fastest)
+ *   4: i1 i2 i3 re    5: i1 i2 i3 re im   every site exactly once, in any order
+ * grid: host, N^3 complex128 (re, im), caller-owned, filled on success.  QFDTD_E_INVALID
+ * (message in qfdtd_last_error(NULL)) for a missing file, a malformed or non-finite number,
+ * an index out of range, a repeated or missing site, or a wrong record count. */
+qfdtd_status qfdtd_read_potential_ascii(const char *path, int32_t N, double *grid);
+
+/* Write N^3 complex128 values as "re im" records in C order (17 significant digits, so
+ * qfdtd_read_potential_ascii returns the same doubles).  QFDTD_E_INVALID if the file cannot
+ * be written. */
+qfdtd_status qfdtd_write_potential_ascii(const char *path, int32_t N, const double *grid);
+
 /* Launch-level timing of the evolution kernels: when enabled, the context records a
  * pair of HIP events on its stream around every sampled launch, per kernel class.
  * qfdtd_kernel_stats returns, for class `cls` (0 plane, 1 row, 2 column, 3 stencil,

@@ -238,3 +238,19 @@ def batch_energies(solvers: Sequence[Solver]):
 
 def footprint(N: int, kinetic: int, precision: int, n_states: int) -> int:
     return int(L.lib.qfdtd_footprint(int(N), int(kinetic), int(precision), int(n_states)))
+
+
+def read_potential_file(path: str, N: int) -> np.ndarray:
+    """Complex potential grid [N, N, N] from an ASCII file (parsed by the library)."""
+    g = np.zeros(2 * N ** 3, dtype=np.float64)
+    L.check(L.lib.qfdtd_read_potential_ascii(str(path).encode(), int(N), g.ctypes.data_as(ct.POINTER(ct.c_double))),
+            None)
+    return (g[0::2] + 1j * g[1::2]).reshape(N, N, N)
+
+
+def write_potential_file(path: str, grid: np.ndarray):
+    """Write a complex grid [N, N, N] as an ASCII potential file (library writer)."""
+    a = np.ascontiguousarray(np.asarray(grid, dtype=np.complex128))
+    N = a.shape[0]
+    L.check(L.lib.qfdtd_write_potential_ascii(str(path).encode(), int(N), a.view(np.float64).ctypes.data_as(
+        ct.POINTER(ct.c_double))), None)

@@ -87,3 +87,52 @@ def test_footprint_scales_with_volume(L):
     assert 7.5 < f2 / f1 < 8.5
     assert L.lib.qfdtd_footprint(128, 1, 1, 3) > f2
     assert L.lib.qfdtd_footprint(0, 1, 0, 3) == 0
+
+
+def test_potential_files_round_trip_in_every_format(tmp_path):
+    from paper_2211_10185_amd.solver import read_potential_file, write_potential_file
+    N = 5
+    g = np.random.default_rng(3)
+    V = g.standard_normal((N, N, N)) * 7 + 1j * g.standard_normal((N, N, N))
+    # library writer -> library reader: the same doubles
+    write_potential_file(tmp_path / "w.txt", V)
+    assert np.array_equal(read_potential_file(tmp_path / "w.txt", N), V)
+    i = np.indices((N, N, N)).reshape(3, -1).T
+    vr, vi = V.real.ravel(), V.imag.ravel()
+    perm = g.permutation(N ** 3)
+    forms = {
+        "re.txt": (np.column_stack([vr]), V.real),
+        "reim.csv": (np.column_stack([vr, vi]), V),
+        "idx_re.txt": (np.column_stack([i, vr])[perm], V.real),
+        "idx_reim.txt": (np.column_stack([i, vr, vi])[perm], V),
+    }
+    for name, (rows, want) in forms.items():
+        sep = "," if name.endswith(".csv") else " "
+        with open(tmp_path / name, "w") as f:
+            f.write("# header line\n\n")
+            for r in rows:
+                f.write(sep.join(repr(float(x)) for x in r) + "  # trailing comment\n")
+        got = read_potential_file(tmp_path / name, N)
+        assert np.array_equal(got, want.astype(np.complex128)), name
+
+
+@pytest.mark.parametrize("content,what", [
+    ("1 2\n3\n", "inconsistent"),
+    ("1 2 3\n", "fields"),
+    ("abc\n", "bad number"),
+    ("", "no records"),
+    ("0 0 0 1\n0 0 0 2\n", "twice"),
+    ("0 0 9 1\n", "range"),
+    ("1\n" * 7, "records"),
+    ("nan 0\n" * 8, "non-finite"),
+])
+def test_potential_file_errors(tmp_path, content, what, L):
+    from paper_2211_10185_amd.solver import read_potential_file
+    p = tmp_path / "bad.txt"
+    p.write_text(content)
+    with pytest.raises(L.QfdtdError) as ei:
+        read_potential_file(p, 2)
+    assert ei.value.status == L.E_INVALID
+    assert what in str(ei.value), str(ei.value)
+    with pytest.raises(L.QfdtdError):
+        read_potential_file(tmp_path / "missing.txt", 2)
