@@ -92,7 +92,10 @@ GroupKernels g_grp[5];
 size_t g_grp_lds[5][3][2];   // per group, kind (plane, row, col), precision: largest LDS of its sizes
 
 hipError_t fft_table_init() {
+  // once per process; contexts may be created from several host threads
+  static std::mutex mu;
   static bool done = false;
+  std::lock_guard<std::mutex> lk(mu);
   if (done) return hipSuccess;
   std::memset(g_fft, 0, sizeof(g_fft));
   std::memset(g_grp, 0, sizeof(g_grp));
@@ -1315,11 +1318,12 @@ qfdtd_status qfdtd_read_potential_ascii(const char *path, int32_t N, double *gri
   int fields = -1;
   size_t rec = 0, line_no = 0, pos = 0;
   double v[6];
+  std::string line;
   while (pos < text.size()) {
     size_t end = text.find('\n', pos);
     if (end == std::string::npos) end = text.size();
     ++line_no;
-    std::string line = text.substr(pos, end - pos);
+    line.assign(text, pos, end - pos);
     pos = end + 1;
     const size_t hash = line.find('#');
     if (hash != std::string::npos) line.resize(hash);
