@@ -202,6 +202,7 @@ def bench_serve(args):
             "config": {"workload": "Poisson serving trace, %d requests at %.0f/s, N in even 2^a3^b5^c [32,256], "
                                    "spline potentials, k=1, dt=0.01, stop at |dE0|<1e-8" % (args.requests, args.rate)},
             "latency_p50_s": out32["latency_p50_s"], "latency_p99_s": out32["latency_p99_s"],
+            "service_p50_s": out32["service_p50_s"], "service_p99_s": out32["service_p99_s"],
             "peak_active": out32["peak_active"],
             "fp64_single_solve": {"solves_per_s": len(reqs) / el64, "latency_p50_s": float(np.percentile(lat64, 50)),
                                   "latency_p99_s": float(np.percentile(lat64, 99))},

@@ -116,9 +116,12 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
         active = keep
     makespan = now()
     lat = np.array([r.latency for r in done]) if done else np.zeros(1)
+    svc = np.array([r.t_done - r.t_admit for r in done]) if done else np.zeros(1)
     return {"results": sorted(done, key=lambda r: r.rid), "makespan_s": makespan,
             "solves_per_s": len(done) / makespan if makespan > 0 else 0.0,
             "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+            # admission -> completion (time on the device, without queueing)
+            "service_p50_s": float(np.percentile(svc, 50)), "service_p99_s": float(np.percentile(svc, 99)),
             "peak_active": peak_active, "peak_footprint_bytes": peak_used, "budget_bytes": budget_bytes,
             "chunks": chunks}
 
