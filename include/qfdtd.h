@@ -122,6 +122,8 @@ typedef struct {
                                      where an x2-x3 plane fits in LDS (schedule autotuning) */
 #define QFDTD_F_NO_GRAPH 4u       /* qfdtd_evolve: launch every chunk directly instead of capturing
                                      a chunk into a HIP graph once and replaying it */
+#define QFDTD_F_THREE_GROUPS 16u  /* FFT kinds, k >= 3: split the states into three groups on three
+                                     internal streams instead of two (schedule autotuning) */
 #define QFDTD_F_AB_SCHEME 8u      /* FFT kinds: step with the legacy update of H_K^(0) with the
                                      FFT kinetic term swapped in (Sec. 2, the update the paper
                                      keeps while changing H_K):  psi' = A psi - B dt H_K psi,

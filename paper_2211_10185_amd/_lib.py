@@ -42,6 +42,7 @@ F_SINGLE_STREAM = 1
 F_ROWCOL = 2
 F_NO_GRAPH = 4
 F_AB_SCHEME = 8
+F_THREE_GROUPS = 16
 
 
 class QfdtdError(RuntimeError):

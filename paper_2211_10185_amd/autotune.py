@@ -6,7 +6,7 @@ step as
     available where an N^2 plane fits in LDS, or
   * the row/column schedule (x3 row pass + three column passes: 4 passes),
 and, with k >= 2 states, either carry all states through one stream or split
-them into two groups pipelined on two streams.  ``tune`` times every candidate
+them into two (or, with k >= 3, three) groups pipelined on their own streams.  ``tune`` times every candidate
 on the device with the solver's own kernels and records the fastest in a JSON
 cache; ``schedule_for`` is what ``Solver`` consults at creation.
 
@@ -46,25 +46,29 @@ def key(N: int, precision: int, k: int) -> str:
 
 def default_schedule(N: int, kinetic: int, precision: int, k: int) -> dict:
     # without a measurement: two streams pay off only once a group's passes fill the GPU
-    return {"rowcol": False, "single_stream": k < 2 or N < 96}
+    single = k < 2 or N < 96
+    return {"rowcol": False, "single_stream": single, "groups": 1 if single else 2}
 
 
 def schedule_for(N: int, kinetic: int, precision: int, k: int) -> dict:
     """Tuned schedule if the cache has one for (N, precision, k), else the default."""
     if kinetic == 0:
-        return {"rowcol": False, "single_stream": True}
+        return {"rowcol": False, "single_stream": True, "groups": 1}
     e = _load().get(key(N, precision, k))
     if e is None:
         return default_schedule(N, kinetic, precision, k)
-    return {"rowcol": bool(e["rowcol"]), "single_stream": bool(e["single_stream"])}
+    single = bool(e["single_stream"])
+    return {"rowcol": bool(e["rowcol"]), "single_stream": single,
+            "groups": 1 if single else int(e.get("groups", 2))}
 
 
 def candidates(N: int, precision: int, k: int):
     out = []
     plane_ok = N <= PLANE_LIMIT[precision]
     for rowcol in ([False, True] if plane_ok else [True]):
-        for single in ([True, False] if (k >= 2 and not rowcol) else [True]):
-            out.append({"rowcol": rowcol, "single_stream": single})
+        groups = [1] if rowcol or k < 2 else ([1, 2, 3] if k >= 3 else [1, 2])
+        for g in groups:
+            out.append({"rowcol": rowcol, "single_stream": g == 1, "groups": g})
     return out
 
 
@@ -75,7 +79,7 @@ def time_schedule(N: int, precision: int, k: int, sched: dict, steps: int = 200,
     from .solver import Solver
     a = 8.0 / N
     s = Solver(N, a, 1.0, kinetic, S.V_HARMONIC, (1.0,), precision=precision, n_states=k,
-               single_stream=sched["single_stream"], rowcol=sched["rowcol"])
+               rowcol=sched["rowcol"], groups=sched.get("groups", 1 if sched["single_stream"] else 2))
     s.set_states(S.initial_states(N, k, 7))
     dt = a * a / 8
     s.evolve(50, dt)
@@ -106,11 +110,13 @@ def tune(sizes: Iterable[int], precisions: Iterable[int] = (0,), states: Iterabl
             for k in states:
                 times = {}
                 for c in candidates(N, prec, k):
-                    name = ("rowcol" if c["rowcol"] else "plane") + ("/1stream" if c["single_stream"] else "/2streams")
+                    name = ("rowcol" if c["rowcol"] else "plane") + ("/1stream" if c["groups"] == 1 else
+                                                                     "/%dstreams" % c["groups"])
                     times[name] = time_schedule(N, prec, k, c, steps)
                 best = min(times, key=times.get)
+                groups = 1 if best.endswith("1stream") else int(best.split("/")[1][0])
                 entries[key(N, prec, k)] = {"rowcol": best.startswith("rowcol"),
-                                            "single_stream": best.endswith("1stream"),
+                                            "single_stream": groups == 1, "groups": groups,
                                             "us_per_step": {n: round(v, 2) for n, v in times.items()}}
                 if verbose:
                     print("tune N=%d prec=%d k=%d -> %s %s" % (N, prec, k, best, entries[key(N, prec, k)]["us_per_step"]),

@@ -177,6 +177,8 @@ int col_tiles(int N, int k, bool dbl) {
 
 }  // namespace
 
+constexpr int MAX_GROUPS = 3;   // state groups of one FFT solve on their own streams
+
 struct qfdtd_ctx {
   int N = 0, kin = 0, prec = 0, k = 0, K = 50;
   double a = 0, m = 0;
@@ -193,11 +195,11 @@ struct qfdtd_ctx {
   double2 *tw64 = nullptr, *scratch64 = nullptr;
   double *ksym64 = nullptr, *v64 = nullptr, *partials = nullptr, *coef = nullptr, *energy = nullptr, *trace = nullptr;
   PassDesc *d_desc = nullptr;   // [0] main, [1] FP64 measurement copy, [2], [3] state groups
-  PassDesc hd[4];
-  int ngroups = 1;              // 2: states split into two groups pipelined on two streams
-  int gk[2] = {0, 0};           // states per group
-  hipStream_t gst[2] = {nullptr, nullptr};
-  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  PassDesc hd[2 + MAX_GROUPS];
+  int ngroups = 1;              // 2 or 3: states split into groups pipelined on their own streams
+  int gk[MAX_GROUPS] = {0, 0, 0};   // states per group
+  hipStream_t gst[MAX_GROUPS] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[MAX_GROUPS] = {nullptr, nullptr, nullptr};
   uint64_t serial = 0;          // unique per context, never reused (keys of batch graphs)
   bool graphs = true;           // capture a steady chunk (passes + orthonormalisation) once, replay it
   std::vector<std::pair<int, hipGraphExec_t>> chunk_graphs;   // keyed by steps in the chunk
@@ -526,8 +528,8 @@ qfdtd_status energies(std::vector<qfdtd_ctx *> &ms, bool with_trace) {
 qfdtd_status run_chunk_grouped(qfdtd_ctx *c, int n) {
   const bool dbl = c->dbl;
   QF_HIP(c, hipEventRecord(c->ev_fork, c->st));
-  for (int g = 0; g < 2; ++g) QF_HIP(c, hipStreamWaitEvent(c->gst[g], c->ev_fork, 0));
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < c->ngroups; ++g) QF_HIP(c, hipStreamWaitEvent(c->gst[g], c->ev_fork, 0));
+  for (int g = 0; g < c->ngroups; ++g) {
     const int which = 2 + g, kg = c->gk[g];
     hipStream_t st = c->gst[g];
     std::vector<Entry> pl{{c, which, M_PRE | M_FWD, plane_tiles(c->N, kg), 0}};
@@ -541,7 +543,7 @@ qfdtd_status run_chunk_grouped(qfdtd_ctx *c, int n) {
     }
     QF_HIP(c, hipEventRecord(c->ev_join[g], st));
   }
-  for (int g = 0; g < 2; ++g) QF_HIP(c, hipStreamWaitEvent(c->st, c->ev_join[g], 0));
+  for (int g = 0; g < c->ngroups; ++g) QF_HIP(c, hipStreamWaitEvent(c->st, c->ev_join[g], 0));
   return QFDTD_OK;
 }
 
@@ -549,7 +551,7 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
   if (ms.empty()) return QFDTD_OK;
   // while launches are timed the state groups run on one stream, so that every timed launch
   // has the device to itself (as under a profiler) and its duration is the kernel's own
-  if (ms.size() == 1 && ms[0]->ngroups == 2 && n[0] > 0 && ms[0]->timer.every <= 0)
+  if (ms.size() == 1 && ms[0]->ngroups >= 2 && n[0] > 0 && ms[0]->timer.every <= 0)
     return run_chunk_grouped(ms[0], n[0]);
   const bool dbl = ms[0]->dbl;
   int maxn = 0;
@@ -615,7 +617,7 @@ qfdtd_status set_dt(qfdtd_ctx *c, double dt) {
   launch_dt_tables(c->dbl, c->v64, c->vcomplex ? 1 : 0, c->N, dt, c->vtab, c->hfac, c->h2fac, c->ktab, c->ksym64,
                    c->kin, c->scheme, c->st);
   QF_LAUNCHED(c);
-  for (int w = 0; w < 4; ++w) {
+  for (int w = 0; w < 2 + MAX_GROUPS; ++w) {
     c->hd[w].dt = dt;
     c->hd[w].stencil_c = dt / (2.0 * c->m * c->a * c->a);
   }
@@ -908,7 +910,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   c->trace_cap = c->trace_on ? 4096 : 0;
 
   auto bail = [&](qfdtd_status s, const std::string &msg) {
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < MAX_GROUPS; ++g) {
       if (c->gst[g]) (void)hipStreamDestroy(c->gst[g]);
       if (c->ev_join[g]) (void)hipEventDestroy(c->ev_join[g]);
     }
@@ -1017,24 +1019,21 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     d.inv_n3 = 1.0 / (double)n3;
   }
   // state groups for the two-stream schedule (plane schedule, k >= 2)
+  for (int g = 0; g < MAX_GROUPS; ++g) c->hd[2 + g] = c->hd[0];
   if (c->fft() && c->plane && c->k >= 2 && !(o.flags & QFDTD_F_SINGLE_STREAM) && !ab) {
-    c->ngroups = 2;
-    c->gk[0] = (c->k + 1) / 2;
-    c->gk[1] = c->k - c->gk[0];
-    for (int g = 0; g < 2; ++g) {
-      c->hd[2 + g] = c->hd[0];
-      c->hd[2 + g].psi = (char *)c->psi + (size_t)(g ? c->gk[0] : 0) * n3 * cs;
+    c->ngroups = ((o.flags & QFDTD_F_THREE_GROUPS) && c->k >= 3) ? 3 : 2;
+    size_t first = 0;
+    bool okg = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int g = 0; g < c->ngroups; ++g) {
+      // states split as evenly as possible, the larger groups first
+      c->gk[g] = c->k / c->ngroups + (g < c->k % c->ngroups ? 1 : 0);
+      c->hd[2 + g].psi = (char *)c->psi + first * n3 * cs;
       c->hd[2 + g].k = c->gk[g];
+      first += (size_t)c->gk[g];
+      okg = okg && hipStreamCreateWithFlags(&c->gst[g], hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&c->ev_join[g], hipEventDisableTiming) == hipSuccess;
     }
-    bool okg = hipStreamCreateWithFlags(&c->gst[0], hipStreamNonBlocking) == hipSuccess &&
-               hipStreamCreateWithFlags(&c->gst[1], hipStreamNonBlocking) == hipSuccess &&
-               hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
-               hipEventCreateWithFlags(&c->ev_join[0], hipEventDisableTiming) == hipSuccess &&
-               hipEventCreateWithFlags(&c->ev_join[1], hipEventDisableTiming) == hipSuccess;
     if (!okg) return bail(QFDTD_E_DEVICE, "stream creation failed");
-  } else {
-    c->hd[2] = c->hd[0];
-    c->hd[3] = c->hd[0];
   }
   if (upload_desc(c) != QFDTD_OK || hipMemsetAsync(c->energy, 0, (2 * MAX_STATES + 8) * 8, c->st) != hipSuccess ||
       hipStreamSynchronize(c->st) != hipSuccess)
@@ -1284,7 +1283,7 @@ void qfdtd_destroy(qfdtd_ctx *c) {
   for (auto &g : c->chunk_graphs) (void)hipGraphExecDestroy(g.second);
   c->chunk_graphs.clear();
   drop_batch_graphs(c->serial);
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < MAX_GROUPS; ++g) {
     if (c->gst[g]) { (void)hipStreamSynchronize(c->gst[g]); (void)hipStreamDestroy(c->gst[g]); }
     if (c->ev_join[g]) (void)hipEventDestroy(c->ev_join[g]);
   }

@@ -321,3 +321,24 @@ def test_potential_from_ascii_file_matches_oracle(tmp_path):
     assert np.max(energy_errors(E, ref["energies"])) < 1e-10
     for j in range(2):
         assert phase_aligned_l2(psi[j], ref["states"][j]) < 1e-9
+
+
+@pytest.mark.parametrize("N", [120, 64])
+def test_state_groups_do_not_change_the_bits(N):
+    # one, two or three state groups on their own streams reorder launches only; every state
+    # sees the same kernels, so energies and states are bit-identical (with graphs on or off)
+    from paper_2211_10185_amd.solver import Solver
+    p = prob(S.K_NR_SIN2, N, k=3, K=20, a=8.0 / N)
+    outs = []
+    for g in (1, 2, 3):
+        for graphs in (False, True):
+            s = solver(p, groups=g, rowcol=False, graphs=graphs)
+            s.set_states(p.init_states())
+            s.evolve(50, p.dt)
+            s.evolve(50, p.dt)
+            assert s.schedule["groups"] == g
+            outs.append(s.states())
+            s.close()
+    for E, psi in outs[1:]:
+        assert np.array_equal(E, outs[0][0])
+        assert np.array_equal(psi, outs[0][1])
