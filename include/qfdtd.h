@@ -18,7 +18,8 @@
  * Readings taken where the paper defers to its references:
  *   - FFT kinds use the symmetric split step  h F^-1[e^{-dt T} F[h psi]],
  *     h = e^{-dt V/2};  H_K^(0) uses psi <- A psi - B dt H_K^(0) psi with
- *     A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2).
+ *     A = (1 - dt V/2)/(1 + dt V/2), B = 1/(1 + dt V/2).  The same A/B update with
+ *     an FFT kinetic term is available as a second scheme (QFDTD_F_AB_SCHEME).
  *   - H_K^(0) is the standard 7-point Laplacian over A^2, times -1/(2M).
  *   - H_K^(3) is evolved and reported with the rest mass removed (T - M).
  *   - Site i_l has coordinate x_l = (i_l - N/2) A (origin on site N/2).
@@ -54,7 +55,8 @@ typedef enum {
   QFDTD_OK = 0,
   QFDTD_E_INVALID = -1,        /* bad argument (null pointer, a <= 0, k out of range, ...) */
   QFDTD_E_UNSUPPORTED_N = -2,  /* N odd, N < 8, N > 512, or (FFT kinds) N not 2^a 3^b 5^c */
-  QFDTD_E_UNSTABLE_DT = -3,    /* dt <= 0, or H_K^(0) with dt > M A^2 / 3 */
+  QFDTD_E_UNSTABLE_DT = -3,    /* dt <= 0, H_K^(0) with dt > M A^2 / 3, or the A/B update of an
+                                  FFT kind above its bound (QFDTD_F_AB_SCHEME) */
   QFDTD_E_NOMEM = -4,          /* device allocation failed */
   QFDTD_E_DEVICE = -5,         /* a HIP runtime call failed */
   QFDTD_E_NUMERIC = -6,        /* NaN/Inf or non-positive norm met during orthonormalisation */
@@ -116,8 +118,8 @@ typedef struct {
 } qfdtd_options;
 
 /* qfdtd_options.flags */
-#define QFDTD_F_SINGLE_STREAM 1u  /* do not split the states of an FFT solve into two
-                                     groups evolved on two internal streams */
+#define QFDTD_F_SINGLE_STREAM 1u  /* do not split the states of an FFT solve into groups
+                                     evolved on internal streams of their own */
 #define QFDTD_F_ROWCOL 2u         /* FFT kinds: use the row + three column pass schedule even
                                      where an x2-x3 plane fits in LDS (schedule autotuning) */
 #define QFDTD_F_NO_GRAPH 4u       /* qfdtd_evolve: launch every chunk directly instead of capturing
@@ -217,7 +219,7 @@ qfdtd_status qfdtd_write_potential_ascii(const char *path, int32_t N, const doub
  * qfdtd_kernel_stats returns, for class `cls` (0 plane, 1 row, 2 column, 3 stencil,
  * 4 measurement), the number of timed launches, their mean duration in ms and the
  * algorithmic bytes one launch of that class moves (read once + written once).
- * While timing is enabled the states of an FFT solve are not split over two internal
+ * While timing is enabled the states of an FFT solve are not split over internal
  * streams, so timed launches never overlap other kernels of the context.  every <= 0
  * disables timing.  Synchronises the stream. */
 qfdtd_status qfdtd_enable_kernel_timing(qfdtd_ctx *c, int32_t every);
@@ -234,7 +236,8 @@ qfdtd_status qfdtd_state_pointer(qfdtd_ctx *c, int32_t i, void **ptr);
 
 void qfdtd_destroy(qfdtd_ctx *c);
 
-/* Message for the last failing call on c (or of the last failed create when c is NULL). */
+/* Message for the last failing call on c, or, when c is NULL, of the last failing
+ * context-free call on this host thread (qfdtd_create, the potential file functions). */
 const char *qfdtd_last_error(const qfdtd_ctx *c);
 
 #ifdef __cplusplus
