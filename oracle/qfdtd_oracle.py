@@ -243,6 +243,28 @@ def step_fdtd(psi: np.ndarray, V: np.ndarray, dt: float, a: float, m: float) -> 
     return A * psi + B * (dt / (2.0 * m * a * a)) * laplacian_dirichlet(psi)
 
 
+def step_fdtd_at(psi: np.ndarray, V_at: np.ndarray, dt: float, a: float, m: float,
+                 sites: np.ndarray) -> np.ndarray:
+    """The H_K^(0) update of ``step_fdtd`` at the given sites only ([n, 3] indices; V_at the
+    potential there), from the six neighbours of each site (zero beyond the walls).  For
+    lattices too large to step whole."""
+    N = psi.shape[0]
+    i1, i2, i3 = sites[:, 0], sites[:, 1], sites[:, 2]
+
+    def at(j1, j2, j3):
+        ok = (j1 >= 0) & (j1 < N) & (j2 >= 0) & (j2 < N) & (j3 >= 0) & (j3 < N)
+        out = np.zeros(len(sites), dtype=np.complex128)
+        out[ok] = psi[j1[ok], j2[ok], j3[ok]]
+        return out
+
+    c = at(i1, i2, i3)
+    lap = (at(i1 + 1, i2, i3) + at(i1 - 1, i2, i3) + at(i1, i2 + 1, i3) + at(i1, i2 - 1, i3)
+           + at(i1, i2, i3 + 1) + at(i1, i2, i3 - 1) - 6.0 * c)
+    A = (1.0 - 0.5 * dt * V_at) / (1.0 + 0.5 * dt * V_at)
+    B = 1.0 / (1.0 + 0.5 * dt * V_at)
+    return A * c + B * (dt / (2.0 * m * a * a)) * lap
+
+
 # --------------------------------------------------------------------------
 # parity projectors and Gram-Schmidt
 # --------------------------------------------------------------------------

@@ -37,7 +37,7 @@ def read_state(s, i):
     return s.state_tensor(i).cpu().numpy().astype(np.complex128)
 
 
-@pytest.mark.parametrize("N,prec", [(32, 0), (48, 0), (80, 0), (96, 0), (128, 0), (160, 0), (250, 0),
+@pytest.mark.parametrize("N,prec", [(32, 0), (48, 0), (80, 0), (96, 0), (128, 0), (160, 0), (250, 0), (256, 1),
                                     (36, 1), (64, 1), (96, 1), (100, 1), (128, 1)])
 def test_transform_matches_oracle_dft(N, prec):
     from paper_2211_10185_amd.solver import Solver, NR_P2, V_HARMONIC

@@ -342,3 +342,31 @@ def test_state_groups_do_not_change_the_bits(N):
     for E, psi in outs[1:]:
         assert np.array_equal(E, outs[0][0])
         assert np.array_equal(psi, outs[0][1])
+
+
+def test_fdtd_at_the_largest_lattice_sampled_against_the_oracle():
+    # N = 512, the largest H_K^(0) lattice (2^27 sites): one step from a seeded complex64 state,
+    # 4000 sampled sites plus walls, edges and corners against the per-site oracle; the output is
+    # normalised, so the comparison is up to one common scale
+    from paper_2211_10185_amd.solver import Solver, FDTD, V_HARMONIC
+    N, a, m = 512, 0.05, 1.0
+    dt = m * a * a / 8
+    psi0 = S.initial_states(N, 1, 512)[0].astype(np.complex64).astype(np.complex128)
+    s = Solver(N, a, m, FDTD, V_HARMONIC, (1.0,), precision=0, n_states=1, measure_every=1)
+    s.set_states(psi0[None])
+    s.evolve(1, dt)
+    _, out = s.states()
+    s.close()
+    g = np.random.default_rng(9)
+    sites = np.concatenate([g.integers(0, N, (4000, 3)),
+                            np.array([[0, 0, 0], [N - 1, N - 1, N - 1], [0, 255, N - 1], [N - 1, 0, 7],
+                                      [256, 256, 256], [1, N - 2, 300]])])
+    x = O.coords(N, a)
+    V_at = 0.5 * (x[sites[:, 0]] ** 2 + x[sites[:, 1]] ** 2 + x[sites[:, 2]] ** 2)
+    want = O.step_fdtd_at(psi0, V_at, dt, a, m, sites)
+    got = out[0][sites[:, 0], sites[:, 1], sites[:, 2]]
+    scale = np.vdot(want, got) / np.vdot(want, want)
+    err = np.linalg.norm(got - scale * want) / np.linalg.norm(scale * want)
+    assert err < 1e-6, err
+    # the scale is the inverse norm of the stepped state: positive real
+    assert abs(scale.imag) < 1e-6 * abs(scale) and scale.real > 0

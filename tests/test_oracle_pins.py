@@ -168,6 +168,20 @@ def test_split_step_equals_dense_exponential(kind):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
+def test_fdtd_update_at_sampled_sites_equals_the_full_step():
+    # the per-site evaluation (for lattices too large to step whole) against the array step,
+    # including sites on every wall, edge and corner
+    N, a, m, dt = 9, 0.4, 1.3, 0.01
+    psi = rnd((N, N, N), 41)
+    V = rnd((N, N, N), 42)
+    full = O.step_fdtd(psi, V, dt, a, m)
+    g = np.random.default_rng(3)
+    sites = np.concatenate([g.integers(0, N, (200, 3)),
+                            np.array([[0, 0, 0], [N - 1, N - 1, N - 1], [0, N - 1, 4], [4, 0, N - 1]])])
+    got = O.step_fdtd_at(psi, V[sites[:, 0], sites[:, 1], sites[:, 2]], dt, a, m, sites)
+    np.testing.assert_allclose(got, full[sites[:, 0], sites[:, 1], sites[:, 2]], rtol=0, atol=1e-14)
+
+
 def test_fdtd_step_at_constant_potential_scales_sine_modes():
     # constant V: the step maps an eigenmode of L_D to ((1 - dt V/2) - dt lam)/(1 + dt V/2) times itself
     N, a, m, dt, v0 = 7, 0.5, 1.0, 0.02, 2.5 + 0.5j
