@@ -9,6 +9,11 @@ by less than ``tol`` since the previous chunk.  Requests that arrived in the
 meantime are admitted at the next chunk boundary while device memory (by the
 library's own footprint estimate) and slots allow, so their work overlaps with
 the solves already running.
+
+A request whose solve fails (a non-finite value or a collapsed norm, reported by
+the library as QFDTD_E_NUMERIC) retires alone with status "failed" while the
+others continue; a request for which ``should_cancel(rid)`` turns true retires at
+the next chunk boundary with status "cancelled".
 """
 from __future__ import annotations
 
@@ -18,6 +23,7 @@ from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
+from . import _lib as L
 from . import solver as S
 
 
@@ -33,6 +39,8 @@ class Result:
     t_admit: float
     t_done: float
     psi: Optional[np.ndarray] = None
+    status: str = "ok"          # "ok", "failed" or "cancelled"
+    error: str = ""
 
     @property
     def latency(self) -> float:
@@ -52,7 +60,8 @@ class _Active:
 def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int] = None,
           max_slots: int = 64, tol: float = 1e-8, max_steps: int = 50000, chunk: Optional[int] = None,
           keep_psi: bool = False, realtime: bool = True,
-          clock: Callable[[], float] = time.perf_counter) -> dict:
+          clock: Callable[[], float] = time.perf_counter,
+          should_cancel: Optional[Callable[[int], bool]] = None) -> dict:
     """Serve ``requests`` (objects with .rid, .arrival (s), .problem); return results and stats.
 
     ``realtime``: admit a request only once the wall clock has passed its arrival
@@ -95,14 +104,55 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
             if wait > 0:
                 time.sleep(min(wait, 0.01))
             continue
+        if should_cancel is not None:
+            keep = []
+            for a in active:
+                if should_cancel(a.req.rid):
+                    done.append(_retire(a, None, False, realtime, now(), "cancelled", ""))
+                    used -= a.footprint
+                else:
+                    keep.append(a)
+            active = keep
+            if not active:
+                continue
         K = chunk or active[0].req.problem.measure_every
         dts = [a.req.problem.dt for a in active]
-        S.batch_evolve([a.solver for a in active], K, dts)
-        E = S.batch_energies([a.solver for a in active])[:, 0]
+        try:
+            S.batch_evolve([a.solver for a in active], K, dts)
+        except L.QfdtdError:
+            # a member failed in an earlier chunk: batch_evolve checks every member before it
+            # launches anything, so no solve advanced; retire the failed one(s) and go on
+            keep = []
+            for a in active:
+                try:
+                    a.solver.energies()
+                    keep.append(a)
+                except L.QfdtdError as err:
+                    done.append(_retire(a, None, False, realtime, now(), "failed", str(err)))
+                    used -= a.footprint
+            if len(keep) == len(active):
+                raise
+            active = keep
+            continue
+        try:
+            E = list(S.batch_energies([a.solver for a in active])[:, 0])
+        except L.QfdtdError:
+            # every member advanced K steps; read them one by one (the same FP64 reductions, so
+            # the same bits) and mark the failed one(s)
+            E = []
+            for a in active:
+                try:
+                    E.append(complex(a.solver.energies()[0]))
+                except L.QfdtdError as err:
+                    E.append(err)
         chunks += 1
         keep = []
         for a, e in zip(active, E):
             a.steps += K
+            if isinstance(e, L.QfdtdError):
+                done.append(_retire(a, None, False, realtime, now(), "failed", str(e)))
+                used -= a.footprint
+                continue
             conv = a.prev is not None and abs(e - a.prev) < tol
             if conv or a.steps >= max_steps:
                 psi = a.solver.states(1)[1][0] if keep_psi else None
@@ -115,15 +165,25 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
                 keep.append(a)
         active = keep
     makespan = now()
-    lat = np.array([r.latency for r in done]) if done else np.zeros(1)
-    svc = np.array([r.t_done - r.t_admit for r in done]) if done else np.zeros(1)
+    ok = [r for r in done if r.status == "ok"]
+    lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    svc = np.array([r.t_done - r.t_admit for r in ok]) if ok else np.zeros(1)
     return {"results": sorted(done, key=lambda r: r.rid), "makespan_s": makespan,
-            "solves_per_s": len(done) / makespan if makespan > 0 else 0.0,
+            "solves_per_s": len(ok) / makespan if makespan > 0 else 0.0,
+            "failed": sum(r.status == "failed" for r in done),
+            "cancelled": sum(r.status == "cancelled" for r in done),
             "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
             # admission -> completion (time on the device, without queueing)
             "service_p50_s": float(np.percentile(svc, 50)), "service_p99_s": float(np.percentile(svc, 99)),
             "peak_active": peak_active, "peak_footprint_bytes": peak_used, "budget_bytes": budget_bytes,
             "chunks": chunks}
+
+
+def _retire(a: _Active, e, conv: bool, realtime: bool, t: float, status: str, error: str) -> Result:
+    a.solver.close()
+    energy = complex(e) if e is not None else complex(np.nan, np.nan)
+    return Result(a.req.rid, a.req.problem.N, a.req.problem.kinetic, energy, a.steps, conv,
+                  a.req.arrival if realtime else 0.0, a.t_admit, t, None, status, error)
 
 
 def solve_alone(req, precision: int = S.C64, tol: float = 1e-8, max_steps: int = 50000,

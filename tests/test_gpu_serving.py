@@ -92,3 +92,31 @@ def test_batch_of_uneven_cornell_lattices_matches_oracle_and_alone():
             assert np.max(energy_errors(E, ref["energies"])) < 1e-5
             for i in range(p.k):
                 assert phase_aligned_l2(psi[i], ref["states"][i]) < 1e-4
+
+
+def test_serving_isolates_a_failed_request_and_cancels_mid_flight():
+    import dataclasses
+    from paper_2211_10185_amd.serving import serve, solve_alone
+    reqs = small_trace(n=5, gap=0.0)
+    # request 2: a grid potential with one non-finite site -> its solve fails in flight
+    p2 = reqs[2].problem
+    V = O.problem_potential(p2)
+    V[3, 4, 5] = np.nan
+    reqs[2] = S.Request(rid=2, arrival=reqs[2].arrival,
+                        problem=dataclasses.replace(p2, vkind=S.V_GRID, grid=V, knots=None))
+    # request 3: cancelled at its third chunk boundary (after two chunks)
+    calls = {}
+
+    def cancel(rid):
+        calls[rid] = calls.get(rid, 0) + 1
+        return rid == 3 and calls[rid] >= 3
+
+    out = serve(reqs, tol=1e-8, max_steps=4000, should_cancel=cancel)
+    res = {r.rid: r for r in out["results"]}
+    assert out["failed"] == 1 and out["cancelled"] == 1
+    assert res[2].status == "failed" and "E_" in res[2].error
+    assert res[3].status == "cancelled" and res[3].steps == 2 * reqs[3].problem.measure_every
+    for rid in (0, 1, 4):
+        alone = solve_alone(reqs[rid], tol=1e-8, max_steps=4000)
+        assert res[rid].status == "ok"
+        assert res[rid].steps == alone.steps and res[rid].energy == alone.energy
