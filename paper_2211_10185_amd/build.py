@@ -19,7 +19,8 @@ OUT = os.path.join(HERE, "libqfdtd.so")
 # (source, object name, extra flags): the transform passes are instantiated
 # per lattice size in five groups so that they compile in parallel
 SOURCES = [("fft_inst.hip", "fft_inst%d" % g, ["-DQF_GROUP=%d" % g]) for g in range(5)] + [
-    ("aux_kernels.hip", "aux_kernels", []), ("qfdtd_api.hip", "qfdtd_api", [])]
+    ("aux_kernels.hip", "aux_kernels", []), ("qfdtd_api.hip", "qfdtd_api", []),
+    ("potential_io.cpp", "potential_io", [])]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code (see the

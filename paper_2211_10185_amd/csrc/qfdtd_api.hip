@@ -53,9 +53,11 @@ void launch_energy_finalize(const LaunchList &L, hipStream_t st);
 
 using namespace qf;
 
-namespace {
+// message of the last failing context-free call on this thread; defined with the
+// potential file I/O (host-only source)
+extern thread_local std::string g_create_error;
 
-thread_local std::string g_create_error;
+namespace {
 
 enum { TC_PLANE = 0, TC_ROW = 1, TC_COL = 2, TC_STENCIL = 3, TC_MEAS = 4, TC_N = 5 };
 
@@ -1296,99 +1298,5 @@ void qfdtd_destroy(qfdtd_ctx *c) {
 
 const char *qfdtd_last_error(const qfdtd_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
-// ASCII potential files.  Records are lines; '#' starts a comment; fields are separated by
-// blanks, tabs or commas.  Every record has the same number of fields:
-//   1: re            2: re im          (N^3 records in C order, x3 fastest)
-//   4: i1 i2 i3 re   5: i1 i2 i3 re im (every site exactly once, any order)
-qfdtd_status qfdtd_read_potential_ascii(const char *path, int32_t N, double *grid) {
-  if (!path || !grid) return fail(nullptr, QFDTD_E_INVALID, "NULL argument");
-  if (N < 1 || N > 1024) return fail(nullptr, QFDTD_E_INVALID, "N must be 1..1024");
-  FILE *f = std::fopen(path, "rb");
-  if (!f) return fail(nullptr, QFDTD_E_INVALID, std::string("cannot open ") + path);
-  std::string text;
-  {
-    char buf[1 << 16];
-    size_t got;
-    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
-    std::fclose(f);
-  }
-  const size_t n3 = (size_t)N * N * N;
-  std::vector<unsigned char> seen;
-  int fields = -1;
-  size_t rec = 0, line_no = 0, pos = 0;
-  double v[6];
-  std::string line;
-  while (pos < text.size()) {
-    size_t end = text.find('\n', pos);
-    if (end == std::string::npos) end = text.size();
-    ++line_no;
-    line.assign(text, pos, end - pos);
-    pos = end + 1;
-    const size_t hash = line.find('#');
-    if (hash != std::string::npos) line.resize(hash);
-    for (char &ch : line)
-      if (ch == ',' || ch == '\t' || ch == '\r') ch = ' ';
-    int nf = 0;
-    const char *p = line.c_str();
-    while (true) {
-      while (*p == ' ') ++p;
-      if (!*p) break;
-      char *q = nullptr;
-      const double x = std::strtod(p, &q);
-      if (q == p || nf == 6) return fail(nullptr, QFDTD_E_INVALID, "bad number or too many fields on line " + std::to_string(line_no));
-      v[nf++] = x;
-      p = q;
-    }
-    if (nf == 0) continue;
-    if (fields < 0) {
-      if (nf != 1 && nf != 2 && nf != 4 && nf != 5)
-        return fail(nullptr, QFDTD_E_INVALID, "records need 1, 2, 4 or 5 fields (line " + std::to_string(line_no) + ")");
-      fields = nf;
-      for (size_t g = 0; g < 2 * n3; ++g) grid[g] = 0.0;
-      if (fields >= 4) seen.assign(n3, 0);
-    } else if (nf != fields) {
-      return fail(nullptr, QFDTD_E_INVALID, "inconsistent field count on line " + std::to_string(line_no));
-    }
-    size_t g;
-    int o = 0;
-    if (fields >= 4) {
-      long long ii[3];
-      for (int a = 0; a < 3; ++a) {
-        if (v[a] != std::floor(v[a]) || v[a] < 0 || v[a] >= N)
-          return fail(nullptr, QFDTD_E_INVALID, "site index out of range on line " + std::to_string(line_no));
-        ii[a] = (long long)v[a];
-      }
-      g = ((size_t)ii[0] * N + (size_t)ii[1]) * N + (size_t)ii[2];
-      if (seen[g]) return fail(nullptr, QFDTD_E_INVALID, "site given twice (line " + std::to_string(line_no) + ")");
-      seen[g] = 1;
-      o = 3;
-    } else {
-      if (rec >= n3) return fail(nullptr, QFDTD_E_INVALID, "more than N^3 records");
-      g = rec;
-    }
-    if (!std::isfinite(v[o]))
-      return fail(nullptr, QFDTD_E_INVALID, "non-finite value on line " + std::to_string(line_no));
-    grid[2 * g] = v[o];
-    grid[2 * g + 1] = (fields == 2 || fields == 5) ? v[o + 1] : 0.0;
-    if (!std::isfinite(grid[2 * g + 1])) return fail(nullptr, QFDTD_E_INVALID, "non-finite value on line " + std::to_string(line_no));
-    ++rec;
-  }
-  if (fields < 0) return fail(nullptr, QFDTD_E_INVALID, "no records");
-  if (rec != n3) return fail(nullptr, QFDTD_E_INVALID, "expected N^3 = " + std::to_string(n3) + " records, found " + std::to_string(rec));
-  return QFDTD_OK;
-}
-
-qfdtd_status qfdtd_write_potential_ascii(const char *path, int32_t N, const double *grid) {
-  if (!path || !grid) return fail(nullptr, QFDTD_E_INVALID, "NULL argument");
-  if (N < 1 || N > 1024) return fail(nullptr, QFDTD_E_INVALID, "N must be 1..1024");
-  FILE *f = std::fopen(path, "wb");
-  if (!f) return fail(nullptr, QFDTD_E_INVALID, std::string("cannot create ") + path);
-  std::fprintf(f, "# complex potential on a %d^3 lattice: re im per site, C order (x3 fastest)\n", N);
-  const size_t n3 = (size_t)N * N * N;
-  bool ok = true;
-  for (size_t g = 0; g < n3 && ok; ++g) ok = std::fprintf(f, "%.17g %.17g\n", grid[2 * g], grid[2 * g + 1]) > 0;
-  ok = (std::fclose(f) == 0) && ok;
-  return ok ? QFDTD_OK : fail(nullptr, QFDTD_E_INVALID, std::string("write failed: ") + path);
-}
 
 }  // extern "C"
