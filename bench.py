@@ -38,11 +38,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-host-io", action="store_true", help="skip the PCIe-inclusive solve after the timed region")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="ho128", choices=["ho128", "ab128", "coulomb", "batch64", "serve"],
+    ap.add_argument("--workload", default="ho128",
+                    choices=["ho128", "ab128", "coulomb", "batch64", "serve", "dft16"],
                     help="ho128: the headline 128^3 workload; ab128: the same problem with H_K^(2) "
                          "stepped by the A/B update; coulomb: the Coulomb validation workload at 128^3; "
                          "batch64: 64 uneven Cornell solves in one batch; "
-                         "serve: Poisson-arrival serving trace")
+                         "serve: Poisson-arrival serving trace; "
+                         "dft16: a batched 16-point DFT stage on the vector ALUs vs FP32 MFMA")
     ap.add_argument("--requests", type=int, default=100, help="serve: number of requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--batch-steps", type=int, default=5000, help="batch64: imaginary-time steps")
@@ -173,6 +175,50 @@ def bench_coulomb(args):
     th = [O.hydrogen_level(n, p.m, 1.0) for n in (1, 2, 2)]
     out["hydrogen_rel_error"] = [round((e - t) / abs(t), 5) for e, t in zip(out["energies"], th)]
     return out
+
+
+def bench_dft16(args):
+    """Batched 16-point DFT stage, FP32: the solver's radix-16 butterfly on the vector ALUs against a
+    dense 16 x 16 complex product on MFMA (v_mfma_f32_16x16x4_f32), 2^20 vectors of 16 points.
+    reps = 64 repetitions in registers time the arithmetic; reps = 1 one stage between HBM read
+    and write.  Accuracy: forward DFT (reps = 1) against torch's FP64 FFT."""
+    import torch
+    from paper_2211_10185_amd import dft_stage as D
+    nvec = 1 << 20
+    g = torch.Generator(device="cuda").manual_seed(16)
+    x = torch.complex(torch.randn(nvec, 16, device="cuda", generator=g),
+                      torch.randn(nvec, 16, device="cuda", generator=g)).contiguous()
+    out = torch.empty_like(x)
+    ref = torch.fft.fft(x.to(torch.complex128), dim=1)
+    res = {}
+    for name in ("valu", "mfma"):
+        y = D.run(x, 1, name)
+        err = ((y.to(torch.complex128) - ref).abs().max() / ref.abs().max()).item()
+        rec = {"rel_err_fwd": err}
+        for reps in (1, 64):
+            D.time_launch(x, out, reps, name, iters=2)          # warm-up
+            ms = D.time_launch(x, out, reps, name, iters=args.steps * 10)
+            rec["reps%d" % reps] = {"ms": round(ms, 4), "dft16_per_s": nvec * reps / (ms * 1e-3)}
+        res[name] = rec
+    r64 = {k: res[k]["reps64"]["dft16_per_s"] for k in res}
+    mfma_tflops = r64["mfma"] * 2048 / 1e12       # 16 MFMA x 2048 flops per tile of 16 vectors
+    valu_nominal = r64["valu"] * 320 / 1e12       # 5 n log2 n nominal flops of a 16-point FFT
+    return {
+        "metric": "16-point DFT stage throughput (FP32, data in registers)", "value": r64["valu"],
+        "unit": "DFT16/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "2^20 vectors x 16 complex64 points, stage repeated 64 times in registers "
+                               "(forward / inverse alternately), VALU butterfly vs MFMA 16x16 product",
+                   "nvec": nvec},
+        "variants": res,
+        "valu_over_mfma": round(r64["valu"] / r64["mfma"], 3),
+        "roofline": {"mfma": {"bound": "mfma", "achieved": round(mfma_tflops, 2), "peak": 157.3,
+                              "unit": "TFLOP/s", "frac": round(mfma_tflops / 157.3, 4)},
+                     "valu": {"bound": "alu", "achieved_nominal": round(valu_nominal, 2), "peak": 157.3,
+                              "unit": "TFLOP/s", "frac": round(valu_nominal / 157.3, 4),
+                              "note": "nominal 320 flops per DFT16 (5 n log2 n); the butterfly executes "
+                                      "156 VALU instructions per DFT16 and lane"}},
+    }
 
 
 def bench_serve(args):
@@ -329,6 +375,9 @@ def main():
         return
     if args.workload == "coulomb":
         print(json.dumps(bench_coulomb(args)), flush=True)
+        return
+    if args.workload == "dft16":
+        print(json.dumps(bench_dft16(args)), flush=True)
         return
     dev = torch.device("cuda:0")
     p_fdtd = S.config2(S.K_FDTD)

@@ -21,6 +21,9 @@ OUT = os.path.join(HERE, "libqfdtd.so")
 SOURCES = [("fft_inst.hip", "fft_inst%d" % g, ["-DQF_GROUP=%d" % g]) for g in range(5)] + [
     ("aux_kernels.hip", "aux_kernels", []), ("qfdtd_api.hip", "qfdtd_api", []),
     ("potential_io.cpp", "potential_io", [])]
+# The DFT-stage measurement tool (VALU butterfly against MFMA), a library of its own
+STAGE_SOURCES = [("dft_stage_bench.hip", "dft_stage_bench", [])]
+STAGE_OUT = os.path.join(HERE, "libdftstage.so")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code (see the
@@ -42,19 +45,23 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    libs = [(OUT, SOURCES), (STAGE_OUT, STAGE_SOURCES)]
     jobs = []
-    for src, name, extra in SOURCES:
-        obj = os.path.join(bdir, name + ".o")
-        jobs.append((obj, [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]))
+    for _, sources in libs:
+        for src, name, extra in sources:
+            obj = os.path.join(bdir, name + ".o")
+            jobs.append((obj, [HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]))
     with cf.ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
         for out in ex.map(lambda j: _run(j[1]), jobs):
             if verbose and out.strip():
                 print(out)
-    tmp = OUT + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [j[0] for j in jobs])
-    os.replace(tmp, OUT)
-    if verbose:
-        print("built", OUT)
+    for lib, sources in libs:
+        tmp = lib + ".tmp"
+        objs = [os.path.join(bdir, name + ".o") for _, name, _ in sources]
+        _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
+        os.replace(tmp, lib)
+        if verbose:
+            print("built", lib)
     return OUT
 
 

@@ -136,3 +136,24 @@ def test_potential_file_errors(tmp_path, content, what, L):
     assert what in str(ei.value), str(ei.value)
     with pytest.raises(L.QfdtdError):
         read_potential_file(tmp_path / "missing.txt", 2)
+
+
+def test_dft_stage_library_exports_its_header():
+    from paper_2211_10185_amd import dft_stage as D
+    txt = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "dft_stage.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(dft16_[a-z_]+)\s*\(", txt)))
+    assert names == D.exported_symbols()
+    for n in names:
+        assert hasattr(D.lib, n), n
+
+
+def test_dft_stage_rejects_invalid_arguments_before_the_device():
+    from paper_2211_10185_amd import dft_stage as D
+    L = D.lib
+    assert L.dft16_stage_run(7, 1, 1, 256, 1, None) == -1          # unknown variant
+    assert L.dft16_stage_run(0, None, 1, 256, 1, None) == -1       # NULL input
+    assert L.dft16_stage_run(0, 1, 1, 100, 1, None) == -1          # not a multiple of 256
+    assert L.dft16_stage_run(1, 1, 1, 256, 0, None) == -1          # reps < 1
+    ms = ct.c_double()
+    assert L.dft16_stage_time(0, 1, 1, 256, 1, 0, None, ct.byref(ms)) == -1
+    assert b"iters" in L.dft16_stage_last_error()
