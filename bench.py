@@ -307,16 +307,22 @@ def copy_ceiling_gbs(nbytes=1 << 30, reps=5):
 
 
 def device_record():
-    """Device name and current clocks (rocm-smi, when present) for the record."""
-    import subprocess
+    """Device name and the current shader and memory clock levels, read from the driver's sysfs
+    files (no helper program is started, so the bench runs unchanged under a profiler)."""
+    import glob
     import torch
-    rec = {"name": torch.cuda.get_device_name(0)}
-    try:
-        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20).stdout
-        rec["clocks"] = [ln.split(":", 1)[-1].strip() for ln in out.splitlines()
-                         if "sclk" in ln or "mclk" in ln or "fclk" in ln][:6]
-    except Exception:
-        rec["clocks"] = None
+    rec = {"name": torch.cuda.get_device_name(0), "clocks": None}
+    clocks = []
+    for kind in ("sclk", "mclk"):
+        for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_%s" % kind))[:1]:
+            try:
+                cur = [ln.strip() for ln in open(path) if ln.strip().endswith("*")]
+            except OSError:
+                cur = []
+            if cur:
+                clocks.append("%s %s" % (kind, cur[0].rstrip("* ").strip()))
+    if clocks:
+        rec["clocks"] = clocks
     return rec
 
 
