@@ -126,6 +126,12 @@ typedef struct {
                                      a chunk into a HIP graph once and replaying it */
 #define QFDTD_F_THREE_GROUPS 16u  /* FFT kinds, k >= 3: split the states into three groups on three
                                      internal streams instead of two (schedule autotuning) */
+#define QFDTD_F_STENCIL_1STEP 32u /* H_K^(0) with complex64 states: one step per stencil pass.
+                                     By default a pass advances two steps at once (eq. HK0
+                                     applied twice in one sweep, the same operations per site,
+                                     so the results are bit-identical) and halves the memory
+                                     traffic per step; a chunk of odd length ends with a
+                                     single step. */
 #define QFDTD_F_AB_SCHEME 8u      /* FFT kinds: step with the legacy update of H_K^(0) with the
                                      FFT kinetic term swapped in (Sec. 2, the update the paper
                                      keeps while changing H_K):  psi' = A psi - B dt H_K psi,

@@ -43,6 +43,7 @@ F_ROWCOL = 2
 F_NO_GRAPH = 4
 F_AB_SCHEME = 8
 F_THREE_GROUPS = 16
+F_STENCIL_1STEP = 32
 
 
 class QfdtdError(RuntimeError):

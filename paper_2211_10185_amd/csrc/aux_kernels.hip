@@ -284,6 +284,171 @@ __global__ void __launch_bounds__(RED_THREADS) k_stencil(const LaunchList L) {
   else stencil_tile<T, false>(sp, dp, d.vtab, N, y0, i3, lane, z0, z1, c, hdt);
 }
 
+// ------------------------------------------------ two fused stencil steps (complex64)
+//
+// psi'' = S(S(psi)) for the H_K^(0) step S above, in one sweep.  A block owns an output tile
+// of S2_TX (x3) x S2_TY (x2) sites over S2_CZ planes along x1 and marches along x1.  At plane
+// zp it
+//   - writes psi(zp) over the tile and a frame of width 2 in x2 and x3 to LDS;
+//   - computes psi'(zp) over the tile and a frame of width 1 (x1 neighbours from registers,
+//     x2 and x3 neighbours from LDS);
+//   - computes psi''(zp - 1) over the tile from psi'(zp - 2), psi'(zp) in registers and
+//     psi'(zp - 1) in LDS, and stores it.
+// Every site is updated with the operations of S in the same order, so the fused pass gives
+// the bits of two single passes.  psi' is zero outside the lattice (the walls).  Per step the
+// lattice is read and written half as often as by single passes.
+constexpr int S2_TX = 64, S2_TY = 16, S2_CZ = 8;   // S2_THREADS: common.h
+constexpr int S2_PX = S2_TX + 4, S2_PY = S2_TY + 4;                // psi plane in LDS
+constexpr int S2_QX = S2_TX + 2, S2_QY = S2_TY + 2;                // psi' plane in LDS
+constexpr int S2_QN = S2_QX * S2_QY;
+constexpr int S2_OWN = (S2_QN + S2_THREADS - 1) / S2_THREADS;      // psi' sites per thread
+constexpr int S2_RING = S2_PX * S2_PY - S2_QN;                     // psi sites outside the psi' tile
+static_assert(S2_RING <= S2_THREADS, "one frame site per thread");
+
+__host__ __device__ inline int stencil2_tiles(int N, int k) {
+  return k * ((N + S2_TX - 1) / S2_TX) * ((N + S2_TY - 1) / S2_TY) * ((N + S2_CZ - 1) / S2_CZ);
+}
+
+// psi-plane coordinates of frame site j: rows 0 and S2_PY - 1, then columns 0 and S2_PX - 1
+// of the rows in between
+__device__ __forceinline__ void s2_frame_site(int j, int &py, int &px) {
+  if (j < S2_PX) { py = 0; px = j; }
+  else if (j < 2 * S2_PX) { py = S2_PY - 1; px = j - S2_PX; }
+  else { const int jj = j - 2 * S2_PX; py = 1 + (jj >> 1); px = (jj & 1) ? S2_PX - 1 : 0; }
+}
+
+template <bool VC>
+__device__ __forceinline__ void stencil2_tile(const float2 *__restrict__ sp, float2 *__restrict__ dp,
+                                              const void *__restrict__ vtab, int N, int x0, int y0, int z0,
+                                              int z1, float c, float hdt, float2 *P, float2 *Q) {
+  using VT = typename VType<float, VC>::type;
+  const int N2 = N * N;
+  const float2 zero = make_float2(0.f, 0.f);
+  VT vzero;
+  if constexpr (VC) vzero = zero; else vzero = 0.f;
+  const int t = threadIdx.x;
+  // psi' sites of this thread: i = t + q S2_THREADS over the (S2_QY x S2_QX) tile
+  int qoff[S2_OWN], pa[S2_OWN], qa[S2_OWN];
+  bool own[S2_OWN], lat[S2_OWN], out[S2_OWN];
+#pragma unroll
+  for (int q = 0; q < S2_OWN; ++q) {
+    const int i = t + q * S2_THREADS;
+    own[q] = i < S2_QN;
+    const int qy = own[q] ? i / S2_QX : 0, qx = own[q] ? i - (i / S2_QX) * S2_QX : 0;
+    const int y = y0 - 1 + qy, x = x0 - 1 + qx;
+    lat[q] = own[q] && y >= 0 && y < N && x >= 0 && x < N;
+    out[q] = lat[q] && qy >= 1 && qy <= S2_TY && qx >= 1 && qx <= S2_TX;
+    qoff[q] = lat[q] ? y * N + x : 0;
+    pa[q] = (qy + 1) * S2_PX + qx + 1;     // its psi-plane address
+    qa[q] = qy * S2_QX + qx;               // its psi'-plane address
+  }
+  // frame site of this thread (psi only)
+  int fa = 0, foff = 0;
+  bool flat = false;
+  if (t < S2_RING) {
+    int py, px;
+    s2_frame_site(t, py, px);
+    const int y = y0 - 2 + py, x = x0 - 2 + px;
+    flat = y >= 0 && y < N && x >= 0 && x < N;
+    foff = flat ? y * N + x : 0;
+    fa = py * S2_PX + px;
+  }
+  auto ld = [&](int z, int off, bool ok) -> float2 {
+    return (ok && z >= 0 && z < N) ? sp[z * N2 + off] : zero;
+  };
+  // registers per psi' site: psi at zp - 1 and zp, psi' at zp - 2 and zp - 1, V at zp - 1
+  float2 pp[S2_OWN], pc[S2_OWN], qm2[S2_OWN], qm1[S2_OWN];
+  VT vm1[S2_OWN];
+#pragma unroll
+  for (int q = 0; q < S2_OWN; ++q) {
+    pp[q] = ld(z0 - 2, qoff[q], lat[q]);
+    pc[q] = ld(z0 - 1, qoff[q], lat[q]);
+    qm2[q] = zero;
+    qm1[q] = zero;
+    vm1[q] = vzero;
+  }
+  for (int zp = z0 - 1; zp <= z1; ++zp) {
+    const bool zin = zp >= 0 && zp < N;
+    float2 pn[S2_OWN];
+    VT v0[S2_OWN];
+#pragma unroll
+    for (int q = 0; q < S2_OWN; ++q) {
+      pn[q] = ld(zp + 1, qoff[q], lat[q]);
+      v0[q] = (lat[q] && zin) ? load_v<float, VC>(vtab, zp * N2 + qoff[q]) : vzero;
+    }
+    const float2 fv = t < S2_RING ? ld(zp, foff, flat) : zero;
+    // psi(zp) over the tile and its frame of width 2
+#pragma unroll
+    for (int q = 0; q < S2_OWN; ++q)
+      if (own[q]) P[pa[q]] = pc[q];
+    if (t < S2_RING) P[fa] = fv;
+    __syncthreads();
+    // psi'(zp) over the tile and its frame of width 1
+    float2 q0[S2_OWN];
+#pragma unroll
+    for (int q = 0; q < S2_OWN; ++q) {
+      q0[q] = zero;
+      if (lat[q] && zin) {
+        const int a = pa[q];
+        const float2 l = P[a - 1], rr = P[a + 1], yu = P[a - S2_PX], yd = P[a + S2_PX];
+        float2 acc = csub(cadd(pp[q], pn[q]), cscale(pc[q], 6.f));
+        acc = cadd(acc, cadd(cadd(l, rr), cadd(yu, yd)));
+        q0[q] = fdtd_update<float, VC>(pc[q], acc, v0[q], c, hdt);
+      }
+    }
+    // psi''(zp - 1) over the tile; the psi' plane in LDS holds psi'(zp - 1)
+    const int zo = zp - 1;
+    if (zo >= z0) {
+#pragma unroll
+      for (int q = 0; q < S2_OWN; ++q) {
+        if (out[q]) {
+          const int a = qa[q];
+          const float2 l = Q[a - 1], rr = Q[a + 1], yu = Q[a - S2_QX], yd = Q[a + S2_QX];
+          float2 acc = csub(cadd(qm2[q], q0[q]), cscale(qm1[q], 6.f));
+          acc = cadd(acc, cadd(cadd(l, rr), cadd(yu, yd)));
+          dp[zo * N2 + qoff[q]] = fdtd_update<float, VC>(qm1[q], acc, vm1[q], c, hdt);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < S2_OWN; ++q) {
+      if (own[q]) Q[qa[q]] = q0[q];
+      pp[q] = pc[q];
+      pc[q] = pn[q];
+      qm2[q] = qm1[q];
+      qm1[q] = q0[q];
+      vm1[q] = v0[q];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(S2_THREADS) k_stencil2(const LaunchList L) {
+  __shared__ float2 P[S2_PX * S2_PY];
+  __shared__ float2 Q[S2_QN];
+  // tiles are ordered as those of the single-step stencil (states of a tile adjacent, runs of
+  // 48 tiles per XCD)
+  const int blk = xcd_block_chunked(blockIdx.x, gridDim.x, 48);
+  const int e = find_entry(L, blk);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const int N = d.N;
+  const int ntx = (N + S2_TX - 1) / S2_TX, nty = (N + S2_TY - 1) / S2_TY;
+  int t = blk - L.tile_start[e];
+  const int s = t % d.k; t /= d.k;
+  const int bx = t % ntx; t /= ntx;
+  const int by = t % nty; t /= nty;
+  const int bz = t;
+  const size_t N3 = (size_t)N * N * N;
+  const float2 *sp = (const float2 *)((mode & M_SWAP) ? d.alt : d.psi) + (size_t)s * N3;
+  float2 *dp = (float2 *)((mode & M_SWAP) ? d.psi : d.alt) + (size_t)s * N3;
+  const float c = (float)d.stencil_c, hdt = (float)(0.5 * d.dt);
+  const int z0 = bz * S2_CZ;
+  const int z1 = (z0 + S2_CZ < N) ? z0 + S2_CZ : N;
+  if (d.vcomplex) stencil2_tile<true>(sp, dp, d.vtab, N, bx * S2_TX, by * S2_TY, z0, z1, c, hdt, P, Q);
+  else stencil2_tile<false>(sp, dp, d.vtab, N, bx * S2_TX, by * S2_TY, z0, z1, c, hdt, P, Q);
+}
+
 // ---------------------------------------------------------------- parity
 
 // reflection of index i on axis: periodic (N - i) mod N; walled N - i (N = wall)
@@ -705,6 +870,8 @@ void launch_to64_slot(bool dbl, double2 *dst, const void *src, size_t n, hipStre
 
 int ew_tiles_host(long long n) { return ew_tiles(n); }
 int stencil_tiles_host(int N, int k) { return stencil_tiles(N, k); }
+int stencil2_tiles_host(int N, int k) { return stencil2_tiles(N, k); }
+const void *stencil2_kernel() { return (const void *)k_stencil2; }
 
 const void *stencil_kernel(bool dbl) {
   return dbl ? (const void *)k_stencil<double> : (const void *)k_stencil<float>;

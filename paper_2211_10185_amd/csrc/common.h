@@ -175,5 +175,6 @@ __host__ __device__ inline int size_group(int N) {
 // Threads per block of each kernel family.
 constexpr int LINE_THREADS = 256;
 constexpr int RED_THREADS = 256;
+constexpr int S2_THREADS = 256;      // block of the two-step stencil
 
 }  // namespace qf

@@ -39,6 +39,8 @@ void launch_from64_slot(bool dbl, void *dst, const double2 *src, size_t n, hipSt
 void launch_to64_slot(bool dbl, double2 *dst, const void *src, size_t n, hipStream_t st);
 int ew_tiles_host(long long n);
 int stencil_tiles_host(int N, int k);
+int stencil2_tiles_host(int N, int k);
+const void *stencil2_kernel();
 const void *stencil_kernel(bool dbl);
 void launch_parity(const LaunchList &L, int total, bool dbl, hipStream_t st);
 void launch_to64(const LaunchList &L, int total, bool dbl, hipStream_t st);
@@ -211,6 +213,7 @@ struct qfdtd_ctx {
   uint32_t set_mask = 0;
   bool poisoned = false;
   int cur = 0;                  // H_K^(0): 1 when the state sits in alt
+  bool stencil2 = false;        // H_K^(0), complex64: two fused steps per stencil pass
   int trace_on = 0;
   int64_t trace_cap = 0, trace_n = 0;
   double *h_status = nullptr;   // pinned
@@ -311,7 +314,7 @@ struct Entry {
   int aux;
 };
 
-enum Fam { F_PLANE, F_ROW, F_COL, F_STENCIL, F_PARITY, F_TO64, F_GRAM, F_APPLY, F_EPART, F_KPART, F_GFIN, F_EFIN };
+enum Fam { F_PLANE, F_ROW, F_COL, F_STENCIL, F_STENCIL2, F_PARITY, F_TO64, F_GRAM, F_APPLY, F_EPART, F_KPART, F_GFIN, F_EFIN };
 
 // algorithmic bytes moved by one member's share of a launch (for timing)
 double entry_bytes(const Entry &e, Fam f) {
@@ -329,6 +332,7 @@ double entry_bytes(const Entry &e, Fam f) {
       return n * (2 * s + ((e.mode & (M_PRE | M_MID | M_POST)) ? fsz : 0.0));
     case F_COL: return n * 2 * s;
     case F_STENCIL: return n * (2 * s + fsz);
+    case F_STENCIL2: return 2 * n * (2 * s + fsz);    // two steps per launch
     default: return n * 2 * s;
   }
 }
@@ -404,7 +408,7 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
     if (f == F_PLANE) cls = TC_PLANE;
     else if (f == F_ROW) cls = TC_ROW;
     else if (f == F_COL) cls = TC_COL;
-    else if (f == F_STENCIL) cls = TC_STENCIL;
+    else if (f == F_STENCIL || f == F_STENCIL2) cls = TC_STENCIL;
     const int tix = cls >= 0 ? tbegin(c0, cls, bytes, st) : -1;
     const FftKernels &K = g_fft[es[base].c->N];
     void *kargs[] = {(void *)&L};
@@ -425,6 +429,7 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
       case F_ROW: go(frow, LINE_THREADS, lds); break;
       case F_COL: go(fcol, LINE_THREADS, lds); break;
       case F_STENCIL: go(stencil_kernel(dbl), RED_THREADS, 0); break;
+      case F_STENCIL2: go(stencil2_kernel(), S2_THREADS, 0); break;
       case F_PARITY: launch_parity(L, total, dbl, st); break;
       case F_TO64: launch_to64(L, total, dbl, st); break;
       case F_GRAM: launch_gram(L, total, KS, dbl, st); break;
@@ -558,7 +563,7 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
   const bool dbl = ms[0]->dbl;
   int maxn = 0;
   for (int v : n) maxn = v > maxn ? v : maxn;
-  std::vector<Entry> pl, rw, c2, c1, sten;
+  std::vector<Entry> pl, rw, c2, c1, sten, sten2;
   // chunk start: h then forward transforms along x3 (and x2)
   for (size_t j = 0; j < ms.size(); ++j) {
     qfdtd_ctx *c = ms[j];
@@ -576,13 +581,18 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
   QF_TRY(run_family(F_ROW, rw, dbl));
   QF_TRY(run_family(F_COL, c2, dbl));
   for (int s = 0; s < maxn; ++s) {
-    c1.clear(); c2.clear(); pl.clear(); rw.clear(); sten.clear();
+    c1.clear(); c2.clear(); pl.clear(); rw.clear(); sten.clear(); sten2.clear();
     std::vector<Entry> c2f;
     for (size_t j = 0; j < ms.size(); ++j) {
       qfdtd_ctx *c = ms[j];
       if (s >= n[j]) continue;
       if (!c->fft()) {
-        sten.push_back({c, 0, c->cur ? (uint32_t)M_SWAP : 0u, stencil_tiles_host(c->N, c->k), 0});
+        // two fused steps at even s while two steps remain; a chunk of odd length ends with
+        // one single step
+        const uint32_t sw = c->cur ? (uint32_t)M_SWAP : 0u;
+        if (c->stencil2 && (s & 1)) continue;                // advanced by the pass at s - 1
+        if (c->stencil2 && s + 1 < n[j]) sten2.push_back({c, 0, sw, stencil2_tiles_host(c->N, c->k), 0});
+        else sten.push_back({c, 0, sw, stencil_tiles_host(c->N, c->k), 0});
         c->cur ^= 1;
         continue;
       }
@@ -604,6 +614,7 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
     QF_TRY(run_family(F_PLANE, pl, dbl));
     QF_TRY(run_family(F_ROW, rw, dbl));
     QF_TRY(run_family(F_COL, c2f, dbl));
+    QF_TRY(run_family(F_STENCIL2, sten2, dbl));
     QF_TRY(run_family(F_STENCIL, sten, dbl));
   }
   return QFDTD_OK;
@@ -908,6 +919,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   if (c->nblk_red < 1) c->nblk_red = 1;
   c->trace_on = o.trace_energies ? 1 : 0;
   c->graphs = !(o.flags & QFDTD_F_NO_GRAPH);
+  c->stencil2 = !c->fft() && !c->dbl && !(o.flags & QFDTD_F_STENCIL_1STEP);
   c->serial = g_next_serial.fetch_add(1);
   c->trace_cap = c->trace_on ? 4096 : 0;
 

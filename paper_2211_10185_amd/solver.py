@@ -79,7 +79,8 @@ class Solver:
                  n_states: int = 3, sectors: Optional[Sequence[int]] = None,
                  measure_every: int = 50, trace: bool = False, torch_alloc: bool = True,
                  single_stream: Optional[bool] = None, rowcol: Optional[bool] = None,
-                 graphs: bool = True, scheme: int = 0, groups: Optional[int] = None):
+                 graphs: bool = True, scheme: int = 0, groups: Optional[int] = None,
+                 fused_stencil: bool = True):
         torch = _torch()
         self.N, self.a, self.m, self.kinetic = int(N), float(a), float(m), int(kinetic)
         self.precision, self.k = int(precision), int(n_states)
@@ -110,7 +111,8 @@ class Solver:
         self.scheme = int(scheme)
         opt.flags = ((L.F_SINGLE_STREAM if single_stream else 0) | (L.F_ROWCOL if rowcol else 0)
                      | (0 if graphs else L.F_NO_GRAPH) | (L.F_AB_SCHEME if self.scheme == 1 else 0)
-                     | (L.F_THREE_GROUPS if int(groups) == 3 else 0))
+                     | (L.F_THREE_GROUPS if int(groups) == 3 else 0)
+                     | (0 if fused_stencil else L.F_STENCIL_1STEP))
         opt.hip_stream = ct.c_void_p(self.stream.cuda_stream)
         if self._alloc is not None:
             opt.dev_alloc = self._alloc.alloc
