@@ -559,30 +559,43 @@ __global__ void __launch_bounds__(RED_THREADS) k_gram(const LaunchList L) {
 
 __device__ __forceinline__ int pair_index(int i, int j, int KS) { return i * KS - i * (i - 1) / 2 + (j - i); }
 
-// Sum of column q of a [nb][2*MAX_PAIRS] partials array over its nb rows with
-// all threads of the block: strided per-thread sums, then a fixed-shape tree.
-// Every thread returns the same value; the order of additions never changes.
-__device__ double block_sum_column(const double *part, int nb, int q) {
-  __shared__ double red[RED_THREADS];
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += RED_THREADS) s += part[(size_t)b * (2 * MAX_PAIRS) + q];
-  red[threadIdx.x] = s;
+// Sums of columns q0 .. q0 + nq - 1 (nq <= SUMQ) of a [nb][2*MAX_PAIRS] partials array over its
+// nb rows, all at once, with all threads of the block: thread t adds rows t, t + RED_THREADS,
+// ... in order, then a fixed-shape tree halves the thread sums.  The order of additions of a
+// column never changes (and does not depend on nq or q0); the loads of all the columns are in
+// flight together.  Thread j < nq writes the sum of column q0 + j to out[j].
+constexpr int SUMQ = 12;
+__device__ void block_sum_columns(const double *part, int nb, int q0, int nq, double *out) {
+  __shared__ double red[SUMQ][RED_THREADS];
+  double s[SUMQ];
+#pragma unroll
+  for (int j = 0; j < SUMQ; ++j) s[j] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RED_THREADS) {
+    const double *row = part + (size_t)b * (2 * MAX_PAIRS) + q0;
+#pragma unroll
+    for (int j = 0; j < SUMQ; ++j)
+      if (j < nq) s[j] += row[j];
+  }
+#pragma unroll
+  for (int j = 0; j < SUMQ; ++j)
+    if (j < nq) red[j][threadIdx.x] = s[j];
   __syncthreads();
   for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int j = 0; j < SUMQ; ++j)
+        if (j < nq) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+    }
     __syncthreads();
   }
-  const double r = red[0];
+  if ((int)threadIdx.x < nq) out[threadIdx.x] = red[threadIdx.x][0];
   __syncthreads();
-  return r;
 }
 
 // The Gram matrix itself: fixed-order sums of the partials into out[nq] (one block).
 __global__ void __launch_bounds__(RED_THREADS) k_gram_sum(const double *partials, int nb, int nq, double *out) {
-  for (int q = 0; q < nq; ++q) {
-    const double v = block_sum_column(partials, nb, q);
-    if (threadIdx.x == 0) out[q] = v;
-  }
+  for (int q0 = 0; q0 < nq; q0 += SUMQ)
+    block_sum_columns(partials, nb, q0, nq - q0 < SUMQ ? nq - q0 : SUMQ, out + q0);
 }
 
 // Sum the partials (fixed order), Cholesky G = R^H R per sector, coef = R^{-1}.
@@ -592,14 +605,13 @@ __global__ void __launch_bounds__(RED_THREADS) k_gram_finalize(const LaunchList 
   const int KS = d.k;
   const int NP = KS * (KS + 1) / 2;
   __shared__ double G[MAX_PAIRS * 2];
-  for (int q = 0; q < 2 * NP; ++q) {
-    const double v = block_sum_column(d.partials, d.nblk_red, q);
-    if (threadIdx.x == 0) G[q] = v;
-  }
-  __syncthreads();
+  for (int q0 = 0; q0 < 2 * NP; q0 += SUMQ)
+    block_sum_columns(d.partials, d.nblk_red, q0, 2 * NP - q0 < SUMQ ? 2 * NP - q0 : SUMQ, G + q0);
+  // the factor and its inverse in LDS: one thread works on them with indices known only at run
+  // time (the states of each sector), which would otherwise put them in scratch memory
+  __shared__ double Rr[MAX_STATES][MAX_STATES], Ri[MAX_STATES][MAX_STATES];
+  __shared__ double Xr[MAX_STATES][MAX_STATES], Xi[MAX_STATES][MAX_STATES];
   if (threadIdx.x != 0) return;
-  double Rr[MAX_STATES][MAX_STATES], Ri[MAX_STATES][MAX_STATES];
-  double Xr[MAX_STATES][MAX_STATES], Xi[MAX_STATES][MAX_STATES];
   for (int i = 0; i < MAX_STATES; ++i)
     for (int j = 0; j < MAX_STATES; ++j) { Rr[i][j] = Ri[i][j] = Xr[i][j] = Xi[i][j] = 0.0; }
   int bad = 0;
@@ -794,13 +806,13 @@ __global__ void __launch_bounds__(RED_THREADS) k_energy_finalize(const LaunchLis
   const int KS = d.k;
   const bool fdtd = d.kin == KIN_FDTD;
   __shared__ double S[6 * MAX_STATES];
-  for (int q = 0; q < 6 * KS; ++q) {
-    double v = 0.0;
-    if (q < 5 * KS) v = block_sum_column(d.partials, d.nblk_red, q);
-    else if (!fdtd) v = block_sum_column(d.partials + (size_t)d.nblk_red * (2 * MAX_PAIRS), d.nblk_red, q - 5 * KS);
-    if (threadIdx.x == 0) S[q] = v;
+  for (int q0 = 0; q0 < 5 * KS; q0 += SUMQ)
+    block_sum_columns(d.partials, d.nblk_red, q0, 5 * KS - q0 < SUMQ ? 5 * KS - q0 : SUMQ, S + q0);
+  if (!fdtd) {
+    for (int q0 = 0; q0 < KS; q0 += SUMQ)
+      block_sum_columns(d.partials + (size_t)d.nblk_red * (2 * MAX_PAIRS), d.nblk_red, q0,
+                        KS - q0 < SUMQ ? KS - q0 : SUMQ, S + 5 * KS + q0);
   }
-  __syncthreads();
   if (threadIdx.x != 0) return;
   const int slot = L.aux[e];
   for (int s = 0; s < KS; ++s) {
