@@ -51,14 +51,11 @@ template <typename T, int N> __host__ __device__ constexpr size_t plane_lds_t() 
 template <typename T, int N> __host__ __device__ constexpr bool plane_fits() {
   return plane_lds_t<T, N>() <= 160 * 1024 && N * N <= 16 * 1024;
 }
-template <int N> __host__ __device__ constexpr int row_block_t() {
-  int rb = 4096 / N;
-  return rb < 1 ? 1 : rb;
-}
+template <typename T, int N> __host__ __device__ constexpr int row_block_t() { return row_block(N, sizeof(T) == 8); }
 template <typename T, int N> __host__ __device__ constexpr size_t row_lds_t() {
-  return (size_t)(row_block_t<N>() * padded_len(N) + tw_total<N>()) * sizeof(C<T>);
+  return (size_t)(row_block_t<T, N>() * padded_len(N) + tw_total<N>()) * sizeof(C<T>);
 }
-template <typename T> __host__ __device__ constexpr int col_tile_t() { return sizeof(T) == 4 ? 16 : 8; }
+template <typename T> __host__ __device__ constexpr int col_tile_t() { return col_tile(sizeof(T) == 8); }
 template <typename T, int N> __host__ __device__ constexpr size_t col_lds_t() {
   return (size_t)(N * (col_tile_t<T>() + 1) + tw_total<N>()) * sizeof(C<T>);
 }
@@ -331,6 +328,18 @@ __global__ void __launch_bounds__(plane_threads<N>()) k_plane_t(const LaunchList
 
 // --------------------------------------------------------------- row pass
 
+// Site offset within its state of element x (< RB N) of a row tile whose first row starts at
+// offset voff0 (< N^3) of its state.  Where a tile spans at most two states (RB N <= N^3, all
+// N >= 16) the offset wraps at most once and one compare replaces a 64-bit remainder per
+// element.
+template <typename T, int N>
+__device__ __forceinline__ size_t row_site(size_t voff0, size_t x) {
+  constexpr size_t N3 = (size_t)N * N * N;
+  const size_t o = voff0 + x;
+  if constexpr ((size_t)row_block_t<T, N>() * N <= N3) return o >= N3 ? o - N3 : o;
+  else return o % N3;
+}
+
 // Steady-state row pass (inverse x3 -> x h^2 -> forward x3): first stage from
 // HBM, last stage to HBM, middle stages fused around the potential factor.
 template <typename T, int N, int NT, int RB, int P, bool AB = false>
@@ -367,11 +376,11 @@ __device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, c
             if constexpr (AB) {
               // A/B update (g is alt): psi' = A psi - B (dt H_K psi), psi read and written at gp
               const size_t o = (size_t)b * N + j + r * SS::NR;
-              const C<T> y = ab_combine<T>(gp[o], v[q][r], d, (voff0 + o) % N3);
+              const C<T> y = ab_combine<T>(gp[o], v[q][r], d, row_site<T, N>(voff0, o));
               gp[o] = y;
               v[q][r] = y;
             } else {
-              v[q][r] = vmul_t<T>(v[q][r], d.h2fac, d.vcomplex, (voff0 + (size_t)b * N + j + r * SS::NR) % N3);
+              v[q][r] = vmul_t<T>(v[q][r], d.h2fac, d.vcomplex, row_site<T, N>(voff0, (size_t)b * N + j + r * SS::NR));
             }
           }
         }
@@ -413,7 +422,7 @@ __device__ __forceinline__ void row_ab(C<T> *buf, const C<T> *tw, const PassDesc
     for (int idx = threadIdx.x; idx < nrows * N; idx += NT) {
       const int r = idx / N, c = idx - r * N;
       const int a = r * P + padn(c);
-      const C<T> o = ab_combine<T>(gp[idx], buf[a], d, (voff0 + idx) % N3);
+      const C<T> o = ab_combine<T>(gp[idx], buf[a], d, row_site<T, N>(voff0, idx));
       gp[idx] = o;
       buf[a] = o;
     }
@@ -433,7 +442,7 @@ __device__ __forceinline__ void row_ab(C<T> *buf, const C<T> *tw, const PassDesc
 template <typename T, int N, int NT>
 __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsigned char *smem) {
   constexpr int P = padded_len(N);
-  constexpr int RB = row_block_t<N>();
+  constexpr int RB = row_block_t<T, N>();
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
   const long long rows_total = (long long)d.k * N * N;
@@ -469,7 +478,7 @@ __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsi
     C<T> v = mkc<T>(0, 0);
     if (r < nrows) {
       v = g[idx];
-      if (mode & M_PRE) v = vmul_t<T>(v, d.hfac, d.vcomplex, (voff0 + idx) % N3);
+      if (mode & M_PRE) v = vmul_t<T>(v, d.hfac, d.vcomplex, row_site<T, N>(voff0, idx));
     }
     buf[r * P + padn(c)] = v;
   }
@@ -480,7 +489,7 @@ __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsi
     for (int idx = threadIdx.x; idx < nrows * N; idx += NT) {
       const int r = idx / N, c = idx - r * N;
       const int a = r * P + padn(c);
-      buf[a] = vmul_t<T>(buf[a], d.h2fac, d.vcomplex, (voff0 + idx) % N3);
+      buf[a] = vmul_t<T>(buf[a], d.h2fac, d.vcomplex, row_site<T, N>(voff0, idx));
     }
     __syncthreads();
   }
@@ -488,7 +497,7 @@ __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsi
   for (int idx = threadIdx.x; idx < nrows * N; idx += NT) {
     const int r = idx / N, c = idx - r * N;
     C<T> v = buf[r * P + padn(c)];
-    if (mode & M_POST) v = vmul_t<T>(v, d.hfac, d.vcomplex, (voff0 + idx) % N3);
+    if (mode & M_POST) v = vmul_t<T>(v, d.hfac, d.vcomplex, row_site<T, N>(voff0, idx));
     g[idx] = v;
   }
 }

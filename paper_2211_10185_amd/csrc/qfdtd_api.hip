@@ -169,13 +169,13 @@ void drop_batch_graphs(uint64_t serial) {
 }
 
 int plane_tiles(int N, int k) { return k * N; }
-int row_tiles(int N, int k) {
+int row_tiles(int N, int k, bool dbl) {
   const long long rows = (long long)k * N * N;
-  const int rb = (4096 / N) < 1 ? 1 : 4096 / N;
+  const int rb = row_block(N, dbl);
   return (int)((rows + rb - 1) / rb);
 }
 int col_tiles(int N, int k, bool dbl) {
-  const int tc = dbl ? 8 : 16;
+  const int tc = col_tile(dbl);
   return k * N * ((N + tc - 1) / tc);
 }
 
@@ -489,7 +489,7 @@ qfdtd_status fwd64(std::vector<qfdtd_ctx *> &ms) {
   for (auto *c : ms) {
     if (c->plane64) pl.push_back({c, 1, M_FWD, plane_tiles(c->N, c->k), 0});
     else {
-      rw.push_back({c, 1, M_FWD, row_tiles(c->N, c->k), 0});
+      rw.push_back({c, 1, M_FWD, row_tiles(c->N, c->k, true), 0});
       c2.push_back({c, 1, M_FWD, col_tiles(c->N, c->k, true), 0});
     }
     c1.push_back({c, 1, M_FWD | M_AXIS1, col_tiles(c->N, c->k, true), 0});
@@ -573,7 +573,7 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
     const uint32_t onalt = c->scheme == SCHEME_AB ? (uint32_t)M_ALT : 0u;
     if (c->plane) pl.push_back({c, 0, start, plane_tiles(c->N, c->k), 0});
     else {
-      rw.push_back({c, 0, start, row_tiles(c->N, c->k), 0});
+      rw.push_back({c, 0, start, row_tiles(c->N, c->k, dbl), 0});
       c2.push_back({c, 0, M_FWD | onalt, col_tiles(c->N, c->k, dbl), 0});
     }
   }
@@ -605,7 +605,7 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
       if (c->plane) pl.push_back({c, 0, rs, plane_tiles(c->N, c->k), 0});
       else {
         c2.push_back({c, 0, M_INV | onalt, col_tiles(c->N, c->k, dbl), 0});
-        rw.push_back({c, 0, rs, row_tiles(c->N, c->k), 0});
+        rw.push_back({c, 0, rs, row_tiles(c->N, c->k, dbl), 0});
         if (!last) c2f.push_back({c, 0, M_FWD | onalt, col_tiles(c->N, c->k, dbl), 0});
       }
     }
@@ -1264,7 +1264,7 @@ qfdtd_status qfdtd_transform_state(qfdtd_ctx *c, int32_t i, int32_t sign) {
   const bool dbl = c->dbl;
   if (c->plane) pl.push_back({c, 0, dir, plane_tiles(c->N, 1), 0});
   else {
-    rw.push_back({c, 0, dir, row_tiles(c->N, 1), 0});
+    rw.push_back({c, 0, dir, row_tiles(c->N, 1, dbl), 0});
     c2.push_back({c, 0, dir, col_tiles(c->N, 1, dbl), 0});
   }
   c1.push_back({c, 0, dir | M_AXIS1 | (sign > 0 ? (uint32_t)M_SCALE : 0u), col_tiles(c->N, 1, dbl), 0});
