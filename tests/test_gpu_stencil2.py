@@ -7,7 +7,8 @@ without it (QFDTD_F_STENCIL_1STEP).  The cases cover:
 - lattices that are not multiples of the 64 x 16 x 8 tile, and one smaller than a tile;
 - a complex potential;
 - chunks of odd length, where a pass of one step ends the chunk;
-- a batch of uneven lattices.
+- a batch of uneven lattices;
+- the largest lattice, 512^3.
 Agreement with the FP64 oracle follows from the FDTD parity tests, which run the fused path.
 """
 import numpy as np
@@ -67,3 +68,28 @@ def test_fused_passes_in_a_batch_of_uneven_lattices():
         s.close()
         assert np.array_equal(Ea, Eb)
         assert np.array_equal(psia, psib)
+
+
+def test_fused_pass_at_the_largest_lattice():
+    # N = 512 (2^27 sites, the largest H_K^(0) lattice): two steps as one fused pass against two
+    # single-step passes, the whole state compared on the device; the single step at this size
+    # is checked against the per-site oracle in the system tests
+    import torch
+    from paper_2211_10185_amd.solver import Solver, FDTD, V_HARMONIC
+    N, a, m = 512, 0.05, 1.0
+    dt = m * a * a / 8
+    print("stencil2 N=512 two steps", flush=True)
+    psi0 = S.initial_states(N, 1, 512)
+    out = []
+    for fused in (True, False):
+        s = Solver(N, a, m, FDTD, V_HARMONIC, (1.0,), precision=0, n_states=1, measure_every=2,
+                   fused_stencil=fused)
+        s.set_states(psi0)
+        s.evolve(2, dt)
+        E = s.energies()
+        out.append((E, s.state_tensor(0).clone()))
+        s.close()
+        torch.cuda.synchronize()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+    assert bool(torch.isfinite(torch.view_as_real(out[0][1])).all())
