@@ -113,3 +113,33 @@ def test_config1_full_run_matches_oracle():
     assert np.max(energy_errors(E, Er)) < 1e-10, (E, Er)
     assert np.max(wavefunction_errors(psi, ref["states"], Er)) < 1e-8
     np.testing.assert_allclose(np.sort(E.real), [1.5, 2.5, 2.5], atol=2e-5)
+
+
+ROW_CASES = [
+    # one row tile holds the rows of all three states (the remainder path of the site index)
+    ("rowcol_p2_ho8_c64", small(S.K_NR_P2, 8, 0, a=0.5, K=7), 30),
+    # row tiles of 85 rows straddle the 144-row states (one wrap of the site index)
+    ("rowcol_sin2_ho12_c128", small(S.K_NR_SIN2, 12, 1, a=0.5, K=7), 30),
+    # tiles of 64 rows over 400-row states, complex potential
+    ("rowcol_rel_cornell20_cV_c64", small(S.K_REL, 20, 0, S.V_CORNELL, (0.4, 0.2, 0.025), a=0.05, m=1.5,
+                                          vgrid_seed=33, K=7, dt=0.05 / 8), 30),
+]
+
+
+@pytest.mark.parametrize("name,p,steps", ROW_CASES, ids=[c[0] for c in ROW_CASES])
+def test_row_schedule_small_lattices_match_oracle(name, p, steps):
+    # the row + three column pass schedule forced on lattices whose planes would fit: row tiles
+    # that span several states or straddle a state boundary
+    print("case", name, flush=True)
+    init = p.init_states()
+    s = gpu_solver(p, rowcol=True)
+    assert s.schedule["rowcol"]
+    s.set_states(init)
+    s.evolve(steps, p.dt)
+    E, psi = s.states()
+    s.close()
+    ref = O.solve(p, steps=steps, init=init)
+    Er, psir = ref["energies"], ref["states"]
+    tol_e, tol_w = (1e-10, 1e-9) if p.precision == 1 else (1e-5, 1e-4)
+    assert np.max(energy_errors(E, Er)) < tol_e, (E, Er)
+    assert np.max(wavefunction_errors(psi, psir, Er)) < tol_w
