@@ -9,22 +9,27 @@
 
 #if QF_GROUP == 0
 #define QF_SIZES(X) X(8) X(10) X(12) X(16) X(18) X(20) X(24) X(30) X(32)
+#define QF_MIN_N 8
 #define QF_PLANE_NT 64
 #define QF_PLANE_NT_D 64
 #elif QF_GROUP == 1
 #define QF_SIZES(X) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(80)
+#define QF_MIN_N 36
 #define QF_PLANE_NT 448
 #define QF_PLANE_NT_D 448
 #elif QF_GROUP == 2
 #define QF_SIZES(X) X(90) X(96) X(100) X(108) X(120) X(128)
+#define QF_MIN_N 90
 #define QF_PLANE_NT 1024
 #define QF_PLANE_NT_D 576
 #elif QF_GROUP == 3
 #define QF_SIZES(X) X(144) X(150) X(160) X(162) X(180)
+#define QF_MIN_N 144
 #define QF_PLANE_NT 64
 #define QF_PLANE_NT_D 64
 #else
 #define QF_SIZES(X) X(192) X(200) X(216) X(240) X(250) X(256)
+#define QF_MIN_N 192
 #define QF_PLANE_NT 64
 #define QF_PLANE_NT_D 64
 #endif
@@ -60,8 +65,10 @@ __global__ void __launch_bounds__(LINE_THREADS) QF_CAT(k_row_multi_g, QF_GROUP)(
 template <typename T>
 __global__ void __launch_bounds__(LINE_THREADS) QF_CAT(k_col_multi_g, QF_GROUP)(const LaunchList L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int e = find_entry(L, blockIdx.x);
-  const int t = blockIdx.x - L.tile_start[e];
+  // the block order of the group's smallest size (the group never straddles COL_XCD_MIN_N)
+  const int blk = col_block(QF_MIN_N);
+  const int e = find_entry(L, blk);
+  const int t = blk - L.tile_start[e];
   switch (((const PassDesc *)L.descp[e])->N) { QF_SIZES(COL_CASE) default: break; }
 }
 
