@@ -184,10 +184,14 @@ constexpr int S2_THREADS = 256;      // block of the two-step stencil
 // per CU).  Measured against a fixed 4096 sites per block: 14-37% faster row passes at most
 // sizes from 150 to 250 (complex64) and 100 to 160 (complex128), the same elsewhere.
 __host__ __device__ constexpr int row_block(int N, bool dbl) {
-  int m = N, a = 0, rmax = 1;
+  int m = N, a = 0, b = 0, c = 0, rmax = 1;
   while (m % 2 == 0) { m /= 2; ++a; }
-  if (m % 5 == 0) rmax = 5;
-  else if (m % 3 == 0) rmax = 3;
+  while (m % 3 == 0) { m /= 3; ++b; }
+  while (m % 5 == 0) { m /= 5; ++c; }
+  // threes are paired into radix-9 stages; fives stay radix 5
+  if (b >= 2) rmax = 9;
+  else if (c >= 1) rmax = 5;
+  else if (b == 1) rmax = 3;
   constexpr int first_pow2_radix[9] = {1, 2, 4, 8, 16, 8, 8, 16, 16};
   if (a <= 8 && first_pow2_radix[a] > rmax) rmax = first_pow2_radix[a];
   int rb = 256 * rmax / N;

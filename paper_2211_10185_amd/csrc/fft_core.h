@@ -35,7 +35,12 @@ constexpr RPlan make_rplan(int N) {
   const int twos[9][2] = {{0, 0}, {2, 0}, {4, 0}, {8, 0}, {16, 0}, {8, 4}, {8, 8}, {16, 8}, {16, 16}};
   for (int i = 0; i < 2; ++i)
     if (a <= 8 && twos[a][i]) p.r[p.n++] = twos[a][i];
-  for (int i = 0; i < b; ++i) p.r[p.n++] = 3;
+  // factors 3 paired into radix-9 stages: fewer stages, so fewer LDS exchanges and barriers
+  // per transform.  (Pairing the fives into radix-25 stages cost 2-4x the registers wherever a
+  // thread holds more than one butterfly, and through the multi-size kernels every size of a
+  // group, so the fives stay radix 5.)
+  for (int i = 0; i < b / 2; ++i) p.r[p.n++] = 9;
+  if (b % 2) p.r[p.n++] = 3;
   for (int i = 0; i < c; ++i) p.r[p.n++] = 5;
   return p;
 }
@@ -172,6 +177,108 @@ template <bool INV, typename V> struct Dft<5, INV, V> {
     v[4] = csub(a1, b1);
     v[2] = cadd(a2, b2);
     v[3] = csub(a2, b2);
+  }
+};
+
+// x * e^{-+ 2 pi i m / NN} for NN = 9 or 25 and a compile-time m (forward sign -, inverse +).
+// The tables hold cos and sin of 2 pi m / NN to 21 digits, with the symmetries
+// cos(2 pi (NN - m)/NN) = cos(2 pi m/NN), sin(2 pi (NN - m)/NN) = -sin(2 pi m/NN) exact.
+template <int M, int NN, bool INV, typename V>
+__device__ __forceinline__ V rot_root(V a) {
+  using T = decltype(a.x);
+  constexpr int m = M % NN;
+  if constexpr (m == 0) {
+    return a;
+  } else {
+    double cm, sm;
+    if constexpr (NN == 9) {
+      constexpr double cs[9] = {1.0, 0.766044443118978035202, 0.173648177666930348852, -0.5,
+                                -0.939692620785908384054, -0.939692620785908384054, -0.5,
+                                0.173648177666930348852, 0.766044443118978035202};
+      constexpr double sn[9] = {0.0, 0.642787609686539326323, 0.984807753012208059367, 0.866025403784438646764,
+                                0.342020143325668733044, -0.342020143325668733044, -0.866025403784438646764,
+                                -0.984807753012208059367, -0.642787609686539326323};
+      cm = cs[m];
+      sm = sn[m];
+    } else {
+      static_assert(NN == 25, "roots of unity of order 9 or 25");
+      constexpr double cs[25] = {
+          1.0, 0.968583161128631119490, 0.876306680043863587308, 0.728968627421411523147,
+          0.535826794978996618271, 0.309016994374947424102, 0.062790519529313376076, -0.187381314585724630543,
+          -0.425779291565072648863, -0.637423989748689710177, -0.809016994374947424102, -0.929776485888251403661,
+          -0.992114701314477831050, -0.992114701314477831050, -0.929776485888251403661, -0.809016994374947424102,
+          -0.637423989748689710177, -0.425779291565072648863, -0.187381314585724630543, 0.062790519529313376076,
+          0.309016994374947424102, 0.535826794978996618271, 0.728968627421411523147, 0.876306680043863587308,
+          0.968583161128631119490};
+      constexpr double sn[25] = {
+          0.0, 0.248689887164854788242, 0.481753674101715274987, 0.684547105928688673732,
+          0.844327925502015078549, 0.951056516295153572116, 0.998026728428271561952, 0.982287250728688681086,
+          0.904827052466019527714, 0.770513242775789230803, 0.587785252292473129169, 0.368124552684677959157,
+          0.125333233564304245373, -0.125333233564304245373, -0.368124552684677959157, -0.587785252292473129169,
+          -0.770513242775789230803, -0.904827052466019527714, -0.982287250728688681086, -0.998026728428271561952,
+          -0.951056516295153572116, -0.844327925502015078549, -0.684547105928688673732, -0.481753674101715274987,
+          -0.248689887164854788242};
+      cm = cs[m];
+      sm = sn[m];
+    }
+    const T c = (T)cm;
+    const T s = INV ? (T)sm : (T)-sm;
+    V r;
+    r.x = fmaT(a.x, c, -(a.y * s));
+    r.y = fmaT(a.x, s, a.y * c);
+    return r;
+  }
+}
+
+// 9 = 3 x 3: DFT3 over n1 of x[3 n1 + n2], twiddle w9^{n2 k1}, DFT3 over n2 -> X[k1 + 3 k2]
+template <bool INV, typename V> struct Dft<9, INV, V> {
+  template <int N2>
+  static __device__ __forceinline__ void col(V *v, V (&y)[3][3]) {
+    V t[3] = {v[N2], v[3 + N2], v[6 + N2]};
+    Dft<3, INV, V>::run(t);
+    y[0][N2] = t[0];
+    y[1][N2] = rot_root<N2, 9, INV>(t[1]);
+    y[2][N2] = rot_root<2 * N2, 9, INV>(t[2]);
+  }
+  static __device__ __forceinline__ void run(V *v) {
+    V y[3][3];
+    col<0>(v, y);
+    col<1>(v, y);
+    col<2>(v, y);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      Dft<3, INV, V>::run(y[k1]);
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2) v[k1 + 3 * k2] = y[k1][k2];
+    }
+  }
+};
+
+// 25 = 5 x 5: DFT5 over n1 of x[5 n1 + n2], twiddle w25^{n2 k1}, DFT5 over n2 -> X[k1 + 5 k2]
+template <bool INV, typename V> struct Dft<25, INV, V> {
+  template <int N2>
+  static __device__ __forceinline__ void col(V *v, V (&y)[5][5]) {
+    V t[5] = {v[N2], v[5 + N2], v[10 + N2], v[15 + N2], v[20 + N2]};
+    Dft<5, INV, V>::run(t);
+    y[0][N2] = t[0];
+    y[1][N2] = rot_root<N2, 25, INV>(t[1]);
+    y[2][N2] = rot_root<2 * N2, 25, INV>(t[2]);
+    y[3][N2] = rot_root<3 * N2, 25, INV>(t[3]);
+    y[4][N2] = rot_root<4 * N2, 25, INV>(t[4]);
+  }
+  static __device__ __forceinline__ void run(V *v) {
+    V y[5][5];
+    col<0>(v, y);
+    col<1>(v, y);
+    col<2>(v, y);
+    col<3>(v, y);
+    col<4>(v, y);
+#pragma unroll
+    for (int k1 = 0; k1 < 5; ++k1) {
+      Dft<5, INV, V>::run(y[k1]);
+#pragma unroll
+      for (int k2 = 0; k2 < 5; ++k2) v[k1 + 5 * k2] = y[k1][k2];
+    }
   }
 };
 
