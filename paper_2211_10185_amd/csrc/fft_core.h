@@ -18,32 +18,7 @@
 
 namespace qf {
 
-// ------------------------------------------------------------- radix plans
-
-struct RPlan {
-  int n;
-  int r[8];
-};
-
-constexpr RPlan make_rplan(int N) {
-  RPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
-  int m = N, a = 0, b = 0, c = 0;
-  while (m % 2 == 0) { m /= 2; ++a; }
-  while (m % 3 == 0) { m /= 3; ++b; }
-  while (m % 5 == 0) { m /= 5; ++c; }
-  // powers of two grouped into as few radix-16/8/4/2 stages as possible
-  const int twos[9][2] = {{0, 0}, {2, 0}, {4, 0}, {8, 0}, {16, 0}, {8, 4}, {8, 8}, {16, 8}, {16, 16}};
-  for (int i = 0; i < 2; ++i)
-    if (a <= 8 && twos[a][i]) p.r[p.n++] = twos[a][i];
-  // factors 3 paired into radix-9 stages: fewer stages, so fewer LDS exchanges and barriers
-  // per transform.  (Pairing the fives into radix-25 stages cost 2-4x the registers wherever a
-  // thread holds more than one butterfly, and through the multi-size kernels every size of a
-  // group, so the fives stay radix 5.)
-  for (int i = 0; i < b / 2; ++i) p.r[p.n++] = 9;
-  if (b % 2) p.r[p.n++] = 3;
-  for (int i = 0; i < c; ++i) p.r[p.n++] = 5;
-  return p;
-}
+// Radix plans: RPlan and make_rplan in common.h (the host's row-tile rule uses them too).
 
 constexpr bool fft_size_ok(int N) {
   int m = N;
@@ -180,7 +155,8 @@ template <bool INV, typename V> struct Dft<5, INV, V> {
   }
 };
 
-// x * e^{-+ 2 pi i m / NN} for NN = 9 or 25 and a compile-time m (forward sign -, inverse +).
+// x * e^{-+ 2 pi i m / NN} for NN = 6, 9, 10, 18 or 25 and a compile-time m (forward sign -,
+// inverse +).
 // The tables hold cos and sin of 2 pi m / NN to 21 digits, with the symmetries
 // cos(2 pi (NN - m)/NN) = cos(2 pi m/NN), sin(2 pi (NN - m)/NN) = -sin(2 pi m/NN) exact.
 template <int M, int NN, bool INV, typename V>
@@ -191,7 +167,37 @@ __device__ __forceinline__ V rot_root(V a) {
     return a;
   } else {
     double cm, sm;
-    if constexpr (NN == 9) {
+    if constexpr (NN == 6) {
+      constexpr double cs[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+      constexpr double sn[6] = {0.0, 0.866025403784438646764, 0.866025403784438646764, 0.0,
+                                -0.866025403784438646764, -0.866025403784438646764};
+      cm = cs[m];
+      sm = sn[m];
+    } else if constexpr (NN == 10) {
+      constexpr double cs[10] = {1.0, 0.809016994374947424102, 0.309016994374947424102, -0.309016994374947424102,
+                                 -0.809016994374947424102, -1.0, -0.809016994374947424102,
+                                 -0.309016994374947424102, 0.309016994374947424102, 0.809016994374947424102};
+      constexpr double sn[10] = {0.0, 0.587785252292473129169, 0.951056516295153572116, 0.951056516295153572116,
+                                 0.587785252292473129169, 0.0, -0.587785252292473129169,
+                                 -0.951056516295153572116, -0.951056516295153572116, -0.587785252292473129169};
+      cm = cs[m];
+      sm = sn[m];
+    } else if constexpr (NN == 18) {
+      constexpr double cs[18] = {1.0, 0.939692620785908384054, 0.766044443118978035202, 0.5,
+                                 0.173648177666930348852, -0.173648177666930348852, -0.5,
+                                 -0.766044443118978035202, -0.939692620785908384054, -1.0,
+                                 -0.939692620785908384054, -0.766044443118978035202, -0.5,
+                                 -0.173648177666930348852, 0.173648177666930348852, 0.5,
+                                 0.766044443118978035202, 0.939692620785908384054};
+      constexpr double sn[18] = {0.0, 0.342020143325668733044, 0.642787609686539326323, 0.866025403784438646764,
+                                 0.984807753012208059367, 0.984807753012208059367, 0.866025403784438646764,
+                                 0.642787609686539326323, 0.342020143325668733044, 0.0,
+                                 -0.342020143325668733044, -0.642787609686539326323, -0.866025403784438646764,
+                                 -0.984807753012208059367, -0.984807753012208059367, -0.866025403784438646764,
+                                 -0.642787609686539326323, -0.342020143325668733044};
+      cm = cs[m];
+      sm = sn[m];
+    } else if constexpr (NN == 9) {
       constexpr double cs[9] = {1.0, 0.766044443118978035202, 0.173648177666930348852, -0.5,
                                 -0.939692620785908384054, -0.939692620785908384054, -0.5,
                                 0.173648177666930348852, 0.766044443118978035202};
@@ -201,7 +207,7 @@ __device__ __forceinline__ V rot_root(V a) {
       cm = cs[m];
       sm = sn[m];
     } else {
-      static_assert(NN == 25, "roots of unity of order 9 or 25");
+      static_assert(NN == 25, "roots of unity of order 6, 9, 10, 18 or 25");
       constexpr double cs[25] = {
           1.0, 0.968583161128631119490, 0.876306680043863587308, 0.728968627421411523147,
           0.535826794978996618271, 0.309016994374947424102, 0.062790519529313376076, -0.187381314585724630543,
@@ -280,6 +286,41 @@ template <bool INV, typename V> struct Dft<25, INV, V> {
       for (int k2 = 0; k2 < 5; ++k2) v[k1 + 5 * k2] = y[k1][k2];
     }
   }
+};
+
+// Radix 2R = 2 x R (R = 3, 5; R = 9 is available but unused): DFT2 over n1 of x[R n1 + n2],
+// twiddle w_{2R}^{n2 k1}, DFT_R over n2 -> X[k1 + 2 k2].  A plan with a single factor 2 merges
+// it into a radix-3 or radix-5 stage, so that the two-point stage does not cost an LDS exchange
+// of its own.
+template <int R, bool INV, typename V, int N2 = 0>
+__device__ __forceinline__ void split2_cols(V *v, V (&y)[2][R]) {
+  if constexpr (N2 < R) {
+    V t[2] = {v[N2], v[R + N2]};
+    Dft<2, INV, V>::run(t);
+    y[0][N2] = t[0];
+    y[1][N2] = rot_root<N2, 2 * R, INV>(t[1]);
+    split2_cols<R, INV, V, N2 + 1>(v, y);
+  }
+}
+template <int R, bool INV, typename V>
+__device__ __forceinline__ void dft_split2(V *v) {
+  V y[2][R];
+  split2_cols<R, INV, V>(v, y);
+#pragma unroll
+  for (int k1 = 0; k1 < 2; ++k1) {
+    Dft<R, INV, V>::run(y[k1]);
+#pragma unroll
+    for (int k2 = 0; k2 < R; ++k2) v[k1 + 2 * k2] = y[k1][k2];
+  }
+}
+template <bool INV, typename V> struct Dft<6, INV, V> {
+  static __device__ __forceinline__ void run(V *v) { dft_split2<3, INV, V>(v); }
+};
+template <bool INV, typename V> struct Dft<10, INV, V> {
+  static __device__ __forceinline__ void run(V *v) { dft_split2<5, INV, V>(v); }
+};
+template <bool INV, typename V> struct Dft<18, INV, V> {
+  static __device__ __forceinline__ void run(V *v) { dft_split2<9, INV, V>(v); }
 };
 
 // ---------------------------------------------------------- line geometry
