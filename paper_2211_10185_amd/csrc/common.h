@@ -60,7 +60,7 @@ struct RPlan {
 // radix-16/8/4/2 stages as possible, threes paired into radix 9 (a leftover 3 alone), fives as
 // radix 5.  A single factor 2 (a = 1) merges into a leftover 3 (radix 6) or a 5 (radix 10) when
 // at least two stages remain (merged into a 9, radix 18 ran N = 162 in complex128 6% slower),
-// and 96 takes 16 x 6.
+// and 60 and 96 take 6 x 10 and 16 x 6.
 __host__ __device__ constexpr RPlan make_rplan(int N) {
   RPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
   int m = N, a = 0, b = 0, c = 0;
@@ -70,6 +70,13 @@ __host__ __device__ constexpr RPlan make_rplan(int N) {
   int nines = b / 2, threes = b % 2, fives = c;
   const bool merge2 = a == 1 && (threes || fives) && nines + threes + fives >= 2;
   const int twos[9][2] = {{0, 0}, {2, 0}, {4, 0}, {8, 0}, {16, 0}, {8, 4}, {8, 8}, {16, 8}, {16, 16}};
+  if (a == 2 && b == 1 && c == 1) {
+    // 60 = 6 x 10: two stages instead of three (4, 3, 5).  (100 = 10 x 10 ran 10-12% faster in
+    // complex64 but 8% slower in complex128, so it keeps 4, 5, 5.)
+    p.r[p.n++] = 6;
+    p.r[p.n++] = 10;
+    return p;
+  }
   if (a == 5 && b == 1 && c == 0) {
     // 96 = 16 x 6: two stages instead of three (8, 4, 3).  (160 = 16 x 10 ran 6-13% faster in
     // complex64 but 3-6% slower in complex128, so it keeps 8, 4, 5.)
