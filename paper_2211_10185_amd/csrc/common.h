@@ -58,35 +58,29 @@ struct RPlan {
 
 // Stages of an N-point transform (N = 2^a 3^b 5^c): powers of two grouped into as few
 // radix-16/8/4/2 stages as possible, threes paired into radix 9 (a leftover 3 alone), fives as
-// radix 5.  A single factor 2 (a = 1) merges into a leftover 3 (radix 6) or a 5 (radix 10) when
-// at least two stages remain (merged into a 9, radix 18 ran N = 162 in complex128 6% slower),
-// and 60 and 96 take 6 x 10 and 16 x 6.
-__host__ __device__ constexpr RPlan make_rplan(int N) {
+// radix 5.  Fewer stages mean fewer LDS exchanges and barriers; larger radices cost registers,
+// which complex128 (dbl) pays twice over, so some merges are for complex64 only:
+//   - a single factor 2 merges into a leftover 3 (radix 6) or a 5 (radix 10) when at least two
+//     stages remain, and for complex64 into a 9 (radix 18, N = 162);
+//   - 60 = 6 x 10 and 96 = 16 x 6; for complex64 also 100 = 10 x 10 and 160 = 16 x 10.
+// The complex64-only merges ran 5-13% faster in complex64 and 3-8% slower in complex128.
+__host__ __device__ constexpr RPlan make_rplan(int N, bool dbl) {
   RPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
   int m = N, a = 0, b = 0, c = 0;
   while (m % 2 == 0) { m /= 2; ++a; }
   while (m % 3 == 0) { m /= 3; ++b; }
   while (m % 5 == 0) { m /= 5; ++c; }
+  if (a == 2 && b == 1 && c == 1) { p.r[p.n++] = 6; p.r[p.n++] = 10; return p; }
+  if (a == 5 && b == 1 && c == 0) { p.r[p.n++] = 16; p.r[p.n++] = 6; return p; }
+  if (!dbl && a == 2 && b == 0 && c == 2) { p.r[p.n++] = 10; p.r[p.n++] = 10; return p; }
+  if (!dbl && a == 5 && b == 0 && c == 1) { p.r[p.n++] = 16; p.r[p.n++] = 10; return p; }
   int nines = b / 2, threes = b % 2, fives = c;
-  const bool merge2 = a == 1 && (threes || fives) && nines + threes + fives >= 2;
+  const bool merge2 = a == 1 && (threes || fives || !dbl) && nines + threes + fives >= 2;
   const int twos[9][2] = {{0, 0}, {2, 0}, {4, 0}, {8, 0}, {16, 0}, {8, 4}, {8, 8}, {16, 8}, {16, 16}};
-  if (a == 2 && b == 1 && c == 1) {
-    // 60 = 6 x 10: two stages instead of three (4, 3, 5).  (100 = 10 x 10 ran 10-12% faster in
-    // complex64 but 8% slower in complex128, so it keeps 4, 5, 5.)
-    p.r[p.n++] = 6;
-    p.r[p.n++] = 10;
-    return p;
-  }
-  if (a == 5 && b == 1 && c == 0) {
-    // 96 = 16 x 6: two stages instead of three (8, 4, 3).  (160 = 16 x 10 ran 6-13% faster in
-    // complex64 but 3-6% slower in complex128, so it keeps 8, 4, 5.)
-    p.r[p.n++] = 16;
-    p.r[p.n++] = 6;
-    return p;
-  }
   if (merge2) {
     if (threes) { p.r[p.n++] = 6; threes = 0; }
-    else { p.r[p.n++] = 10; --fives; }
+    else if (fives) { p.r[p.n++] = 10; --fives; }
+    else { p.r[p.n++] = 18; --nines; }
   } else {
     for (int i = 0; i < 2; ++i)
       if (a <= 8 && twos[a][i]) p.r[p.n++] = twos[a][i];
@@ -232,7 +226,7 @@ constexpr int S2_THREADS = 256;      // block of the two-step stencil
 // per CU).  Measured against a fixed 4096 sites per block: 14-37% faster row passes at most
 // sizes from 150 to 250 (complex64) and 100 to 160 (complex128), the same elsewhere.
 __host__ __device__ constexpr int row_block(int N, bool dbl) {
-  const RPlan p = make_rplan(N);
+  const RPlan p = make_rplan(N, dbl);
   int rmax = 1;
   for (int i = 0; i < p.n; ++i)
     if (p.r[i] > rmax) rmax = p.r[i];

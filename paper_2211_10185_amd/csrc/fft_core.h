@@ -351,8 +351,8 @@ template <int NL, int P> struct ColsGeo {
 // lanes stride through it and collide on LDS banks).  Tables of the radix
 // plan come first, then those of the reversed plan.
 
-template <int N, bool REV> __host__ __device__ constexpr RPlan plan_of() {
-  RPlan p = make_rplan(N);
+template <typename T, int N, bool REV> __host__ __device__ constexpr RPlan plan_of() {
+  RPlan p = make_rplan(N, sizeof(T) == 8);
   if (REV) {
     RPlan q = p;
     for (int i = 0; i < p.n; ++i) q.r[i] = p.r[p.n - 1 - i];
@@ -360,13 +360,13 @@ template <int N, bool REV> __host__ __device__ constexpr RPlan plan_of() {
   }
   return p;
 }
-template <int N, bool REV, int S> __host__ __device__ constexpr int ns_before() {
+template <typename T, int N, bool REV, int S> __host__ __device__ constexpr int ns_before() {
   int ns = 1;
-  for (int i = 0; i < S; ++i) ns *= plan_of<N, REV>().r[i];
+  for (int i = 0; i < S; ++i) ns *= plan_of<T, N, REV>().r[i];
   return ns;
 }
-template <int N, bool REV> __host__ __device__ constexpr int tw_plan_size() {
-  constexpr RPlan p = plan_of<N, REV>();
+template <typename T, int N, bool REV> __host__ __device__ constexpr int tw_plan_size() {
+  constexpr RPlan p = plan_of<T, N, REV>();
   int sz = 0, ns = 1;
   for (int i = 0; i < p.n; ++i) {
     if (ns > 1) sz += (p.r[i] - 1) * ns;
@@ -374,10 +374,10 @@ template <int N, bool REV> __host__ __device__ constexpr int tw_plan_size() {
   }
   return sz;
 }
-template <int N> __host__ __device__ constexpr int tw_total() { return tw_plan_size<N, false>() + tw_plan_size<N, true>(); }
-template <int N, bool REV, int S> __host__ __device__ constexpr int tw_off() {
-  constexpr RPlan p = plan_of<N, REV>();
-  int off = REV ? tw_plan_size<N, false>() : 0, ns = 1;
+template <typename T, int N> __host__ __device__ constexpr int tw_total() { return tw_plan_size<T, N, false>() + tw_plan_size<T, N, true>(); }
+template <typename T, int N, bool REV, int S> __host__ __device__ constexpr int tw_off() {
+  constexpr RPlan p = plan_of<T, N, REV>();
+  int off = REV ? tw_plan_size<T, N, false>() : 0, ns = 1;
   for (int i = 0; i < S; ++i) {
     if (ns > 1) off += (p.r[i] - 1) * ns;
     ns *= p.r[i];
@@ -387,12 +387,12 @@ template <int N, bool REV, int S> __host__ __device__ constexpr int tw_off() {
 
 template <typename T, int N, bool REV, int NT, int S>
 __device__ __forceinline__ void fill_tw_plan(C<T> *lt, const C<T> *gtw) {
-  constexpr RPlan p = plan_of<N, REV>();
+  constexpr RPlan p = plan_of<T, N, REV>();
   if constexpr (S < p.n) {
     constexpr int R = p.r[S];
-    constexpr int NS = ns_before<N, REV, S>();
+    constexpr int NS = ns_before<T, N, REV, S>();
     if constexpr (NS > 1) {
-      constexpr int off = tw_off<N, REV, S>();
+      constexpr int off = tw_off<T, N, REV, S>();
       constexpr int twstep = N / (NS * R);
       for (int i = threadIdx.x; i < (R - 1) * NS; i += NT) {
         const int r = i / NS + 1, kk = i - (r - 1) * NS;
@@ -461,10 +461,10 @@ __device__ __forceinline__ void tstage(C<T> *buf, const C<T> *tw) {
 
 template <typename T, int N, bool INV, class G, int NT, int S, int NS>
 __device__ __forceinline__ void run_stages(C<T> *buf, const C<T> *tw) {
-  constexpr RPlan P = make_rplan(N);
+  constexpr RPlan P = make_rplan(N, sizeof(T) == 8);
   if constexpr (S < P.n) {
     constexpr int R = P.r[S];
-    tstage<T, N, R, NS, INV, G, NT, tw_off<N, false, S>()>(buf, tw);
+    tstage<T, N, R, NS, INV, G, NT, tw_off<T, N, false, S>()>(buf, tw);
     run_stages<T, N, INV, G, NT, S + 1, NS * R>(buf, tw);
   }
 }
@@ -543,10 +543,10 @@ __device__ __forceinline__ void st_write(C<T> (&v)[CQ][R], Dst dst) {
 template <typename T, int N, bool REV, bool INV, class G, int NT, int S0, int S1>
 __device__ __forceinline__ void lds_stages(C<T> *buf, const C<T> *tw) {
   if constexpr (S0 < S1) {
-    constexpr int R = plan_of<N, REV>().r[S0];
-    constexpr int NS = ns_before<N, REV, S0>();
+    constexpr int R = plan_of<T, N, REV>().r[S0];
+    constexpr int NS = ns_before<T, N, REV, S0>();
     C<T> v[SG<G, N, R, NT>::CAPQ][R];
-    st_read<T, N, R, NS, INV, G, NT, tw_off<N, REV, S0>()>(v, tw, [&](int b, int n) { return buf[G::at(b, n)]; });
+    st_read<T, N, R, NS, INV, G, NT, tw_off<T, N, REV, S0>()>(v, tw, [&](int b, int n) { return buf[G::at(b, n)]; });
     __syncthreads();
     st_write<T, N, R, NS, G, NT>(v, [&](int b, int n, C<T> x) { buf[G::at(b, n)] = x; });
     __syncthreads();

@@ -46,18 +46,18 @@ template <typename T, int N> __host__ __device__ constexpr int plane_pitch() {
   }
 }
 template <typename T, int N> __host__ __device__ constexpr size_t plane_lds_t() {
-  return (size_t)(N * plane_pitch<T, N>() + tw_total<N>()) * sizeof(C<T>);
+  return (size_t)(N * plane_pitch<T, N>() + tw_total<T, N>()) * sizeof(C<T>);
 }
 template <typename T, int N> __host__ __device__ constexpr bool plane_fits() {
   return plane_lds_t<T, N>() <= 160 * 1024 && N * N <= 16 * 1024;
 }
 template <typename T, int N> __host__ __device__ constexpr int row_block_t() { return row_block(N, sizeof(T) == 8); }
 template <typename T, int N> __host__ __device__ constexpr size_t row_lds_t() {
-  return (size_t)(row_block_t<T, N>() * padded_len(N) + tw_total<N>()) * sizeof(C<T>);
+  return (size_t)(row_block_t<T, N>() * padded_len(N) + tw_total<T, N>()) * sizeof(C<T>);
 }
 template <typename T> __host__ __device__ constexpr int col_tile_t() { return col_tile(sizeof(T) == 8); }
 template <typename T, int N> __host__ __device__ constexpr size_t col_lds_t() {
-  return (size_t)(N * (col_tile_t<T>() + 1) + tw_total<N>()) * sizeof(C<T>);
+  return (size_t)(N * (col_tile_t<T>() + 1) + tw_total<T, N>()) * sizeof(C<T>);
 }
 
 // psi * f where f is real (T) or complex (C<T>) at site `off`.
@@ -135,7 +135,7 @@ __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, 
                                              C<T> *gp = nullptr) {
   using Rows = RowsGeo<N, P>;
   using Cols = ColsGeo<N, P>;
-  constexpr RPlan PL = plan_of<N, false>();
+  constexpr RPlan PL = plan_of<T, N, false>();
   constexpr int M = PL.n - 1;
   // potential factors of the fused middle stage, fetched before any transform
   // work so their latency overlaps the inverse transforms
@@ -165,10 +165,10 @@ __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, 
   lds_stages<T, N, false, true, Rows, NT, 0, M>(pl, tw);
   {
     constexpr int R = PL.r[M];
-    constexpr int NSL = ns_before<N, false, M>();
+    constexpr int NSL = ns_before<T, N, false, M>();
     using S = SG<Rows, N, R, NT>;
     C<T> v[S::CAPQ][R];
-    st_read<T, N, R, NSL, true, Rows, NT, tw_off<N, false, M>()>(v, tw, [&](int b, int n) { return pl[Rows::at(b, n)]; });
+    st_read<T, N, R, NSL, true, Rows, NT, tw_off<T, N, false, M>()>(v, tw, [&](int b, int n) { return pl[Rows::at(b, n)]; });
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < S::CAPQ; ++q) {
@@ -198,10 +198,10 @@ __device__ __forceinline__ void plane_steady(C<T> *pl, const C<T> *tw, C<T> *g, 
   lds_stages<T, N, true, false, Rows, NT, 1, PL.n>(pl, tw);
   lds_stages<T, N, true, false, Cols, NT, 0, M>(pl, tw);
   {
-    constexpr int R = plan_of<N, true>().r[M];
-    constexpr int NSL = ns_before<N, true, M>();
+    constexpr int R = plan_of<T, N, true>().r[M];
+    constexpr int NSL = ns_before<T, N, true, M>();
     C<T> v[SG<Cols, N, R, NT>::CAPQ][R];
-    st_read<T, N, R, NSL, false, Cols, NT, tw_off<N, true, M>()>(v, tw, [&](int b, int n) { return pl[Cols::at(b, n)]; });
+    st_read<T, N, R, NSL, false, Cols, NT, tw_off<T, N, true, M>()>(v, tw, [&](int b, int n) { return pl[Cols::at(b, n)]; });
     st_write<T, N, R, NSL, Cols, NT>(v, [&](int b, int n, C<T> x) { g[n * N + b] = x; });
   }
 }
@@ -267,7 +267,7 @@ __device__ __forceinline__ void plane_body(const LaunchList &L, int e, int t, un
   C<T> *g = (C<T> *)d.psi + ((size_t)s * N + i1) * N2;
   const size_t voff = (size_t)i1 * N2;
   if (mode & (M_COMB | M_ALT)) {
-    if constexpr (plan_of<N, false>().n >= 2) {
+    if constexpr (plan_of<T, N, false>().n >= 2) {
       if (mode == (M_INV | M_COMB | M_FWD | M_ALT)) {
         __syncthreads();
         C<T> *ga = (C<T> *)d.alt + ((size_t)s * N + i1) * N2;
@@ -278,7 +278,7 @@ __device__ __forceinline__ void plane_body(const LaunchList &L, int e, int t, un
     plane_ab<T, N, NT, P>(pl, tw, d, mode, s, i1);
     return;
   }
-  if constexpr (plan_of<N, false>().n >= 2) {
+  if constexpr (plan_of<T, N, false>().n >= 2) {
     if (mode == (M_INV | M_MID | M_FWD)) {
       __syncthreads();
       if (d.vcomplex) plane_steady<T, N, NT, P, true>(pl, tw, g, d, voff);
@@ -346,7 +346,7 @@ template <typename T, int N, int NT, int RB, int P, bool AB = false>
 __device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, const PassDesc &d, size_t voff0,
                                            int nrows, C<T> *gp = nullptr) {
   using Rows = RowsGeo<RB, P>;
-  constexpr RPlan PL = plan_of<N, false>();
+  constexpr RPlan PL = plan_of<T, N, false>();
   constexpr int M = PL.n - 1;
   constexpr size_t N3 = (size_t)N * N * N;
   const C<T> zero = mkc<T>(0, 0);
@@ -360,10 +360,10 @@ __device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, c
   lds_stages<T, N, false, true, Rows, NT, 1, M>(buf, tw);
   {
     constexpr int R = PL.r[M];
-    constexpr int NSL = ns_before<N, false, M>();
+    constexpr int NSL = ns_before<T, N, false, M>();
     using SS = SG<Rows, N, R, NT>;
     C<T> v[SS::CAPQ][R];
-    st_read<T, N, R, NSL, true, Rows, NT, tw_off<N, false, M>()>(v, tw, [&](int b, int n) { return buf[Rows::at(b, n)]; });
+    st_read<T, N, R, NSL, true, Rows, NT, tw_off<T, N, false, M>()>(v, tw, [&](int b, int n) { return buf[Rows::at(b, n)]; });
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < SS::CAPQ; ++q) {
@@ -392,10 +392,10 @@ __device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, c
   }
   lds_stages<T, N, true, false, Rows, NT, 1, M>(buf, tw);
   {
-    constexpr int R = plan_of<N, true>().r[M];
-    constexpr int NSL = ns_before<N, true, M>();
+    constexpr int R = plan_of<T, N, true>().r[M];
+    constexpr int NSL = ns_before<T, N, true, M>();
     C<T> v[SG<Rows, N, R, NT>::CAPQ][R];
-    st_read<T, N, R, NSL, false, Rows, NT, tw_off<N, true, M>()>(v, tw, [&](int b, int n) { return buf[Rows::at(b, n)]; });
+    st_read<T, N, R, NSL, false, Rows, NT, tw_off<T, N, true, M>()>(v, tw, [&](int b, int n) { return buf[Rows::at(b, n)]; });
     st_write<T, N, R, NSL, Rows, NT>(v, [&](int b, int n, C<T> x) {
       if (b < nrows) g[b * N + n] = x;
     });
@@ -456,7 +456,7 @@ __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsi
   // site offset of the tile's first row within its state; (voff0 + idx) % N^3 wraps at state boundaries
   const size_t voff0 = (size_t)(row0 % (long long)(N * N)) * N;
   if (mode & (M_COMB | M_ALT)) {
-    if constexpr (plan_of<N, false>().n >= 2) {
+    if constexpr (plan_of<T, N, false>().n >= 2) {
       if (mode == (M_INV | M_COMB | M_FWD | M_ALT)) {
         __syncthreads();
         row_steady<T, N, NT, RB, P, true>(buf, tw, (C<T> *)d.alt + (size_t)row0 * N, d, voff0, nrows, g);
@@ -466,7 +466,7 @@ __device__ __forceinline__ void row_body(const LaunchList &L, int e, int t, unsi
     row_ab<T, N, NT, RB, P>(buf, tw, d, mode, row0, nrows, voff0);
     return;
   }
-  if constexpr (plan_of<N, false>().n >= 2) {
+  if constexpr (plan_of<T, N, false>().n >= 2) {
     if (mode == (M_INV | M_MID | M_FWD)) {
       __syncthreads();
       row_steady<T, N, NT, RB, P>(buf, tw, g, d, voff0, nrows);
@@ -523,7 +523,7 @@ template <int NL, int PC> struct TileGeo {
 template <typename T, int N, int NT, class Geo>
 __device__ __forceinline__ void col_steady(C<T> *buf, const C<T> *tw, C<T> *g, size_t S, const PassDesc &d, bool ax1,
                                            int o, int c0, int nc) {
-  constexpr RPlan PL = plan_of<N, false>();
+  constexpr RPlan PL = plan_of<T, N, false>();
   constexpr int M = PL.n - 1;
   constexpr int TC = Geo::nlines;
   const C<T> zero = mkc<T>(0, 0);
@@ -538,10 +538,10 @@ __device__ __forceinline__ void col_steady(C<T> *buf, const C<T> *tw, C<T> *g, s
   lds_stages<T, N, false, false, Geo, NT, 1, M>(buf, tw);
   {
     constexpr int R = PL.r[M];
-    constexpr int NSL = ns_before<N, false, M>();
+    constexpr int NSL = ns_before<T, N, false, M>();
     using SS = SG<Geo, N, R, NT>;
     C<T> v[SS::CAPQ][R];
-    st_read<T, N, R, NSL, false, Geo, NT, tw_off<N, false, M>()>(v, tw, [&](int b, int n) { return buf[Geo::at(b, n)]; });
+    st_read<T, N, R, NSL, false, Geo, NT, tw_off<T, N, false, M>()>(v, tw, [&](int b, int n) { return buf[Geo::at(b, n)]; });
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < SS::CAPQ; ++q) {
@@ -562,10 +562,10 @@ __device__ __forceinline__ void col_steady(C<T> *buf, const C<T> *tw, C<T> *g, s
   }
   lds_stages<T, N, true, true, Geo, NT, 1, M>(buf, tw);
   {
-    constexpr int R = plan_of<N, true>().r[M];
-    constexpr int NSL = ns_before<N, true, M>();
+    constexpr int R = plan_of<T, N, true>().r[M];
+    constexpr int NSL = ns_before<T, N, true, M>();
     C<T> v[SG<Geo, N, R, NT>::CAPQ][R];
-    st_read<T, N, R, NSL, true, Geo, NT, tw_off<N, true, M>()>(v, tw, [&](int b, int n) { return buf[Geo::at(b, n)]; });
+    st_read<T, N, R, NSL, true, Geo, NT, tw_off<T, N, true, M>()>(v, tw, [&](int b, int n) { return buf[Geo::at(b, n)]; });
     st_write<T, N, R, NSL, Geo, NT>(v, [&](int b, int n, C<T> x) {
       if (N % TC == 0 || b < nc) g[(size_t)n * S + b] = x;
     });
@@ -576,7 +576,7 @@ __device__ __forceinline__ void col_steady(C<T> *buf, const C<T> *tw, C<T> *g, s
 // first stage from HBM, last stage to HBM.
 template <typename T, int N, int NT, class Geo, bool INV>
 __device__ __forceinline__ void col_single(C<T> *buf, const C<T> *tw, C<T> *g, size_t S, int nc, T post) {
-  constexpr RPlan PL = plan_of<N, false>();
+  constexpr RPlan PL = plan_of<T, N, false>();
   constexpr int M = PL.n - 1;
   constexpr int TC = Geo::nlines;
   const C<T> zero = mkc<T>(0, 0);
@@ -591,9 +591,9 @@ __device__ __forceinline__ void col_single(C<T> *buf, const C<T> *tw, C<T> *g, s
   lds_stages<T, N, false, INV, Geo, NT, 1, M>(buf, tw);
   {
     constexpr int R = PL.r[M];
-    constexpr int NSL = ns_before<N, false, M>();
+    constexpr int NSL = ns_before<T, N, false, M>();
     C<T> v[SG<Geo, N, R, NT>::CAPQ][R];
-    st_read<T, N, R, NSL, INV, Geo, NT, tw_off<N, false, M>()>(v, tw, [&](int b, int n) { return buf[Geo::at(b, n)]; });
+    st_read<T, N, R, NSL, INV, Geo, NT, tw_off<T, N, false, M>()>(v, tw, [&](int b, int n) { return buf[Geo::at(b, n)]; });
     st_write<T, N, R, NSL, Geo, NT>(v, [&](int b, int n, C<T> x) {
       if (N % TC == 0 || b < nc) g[(size_t)n * S + b] = cscale(x, post);
     });
@@ -622,7 +622,7 @@ __device__ __forceinline__ void col_body(const LaunchList &L, int e, int t, unsi
   load_tw<T, N, NT>(tw, d);
   C<T> *g = (C<T> *)((mode & M_ALT) ? d.alt : d.psi) + (size_t)s * N * N * N + (size_t)o * OS + c0;
   using Geo = TileGeo<TC, PC>;
-  if constexpr (plan_of<N, false>().n >= 2) {
+  if constexpr (plan_of<T, N, false>().n >= 2) {
     const int nc = (N - c0) < TC ? (N - c0) : TC;
     const uint32_t m3 = mode & (M_FWD | M_KIN | M_INV);
     if (m3 == (M_FWD | M_KIN | M_INV) && !(mode & M_SCALE)) {
