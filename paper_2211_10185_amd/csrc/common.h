@@ -62,7 +62,8 @@ struct RPlan {
 // which complex128 (dbl) pays twice over, so some merges are for complex64 only:
 //   - a single factor 2 merges into a leftover 3 (radix 6) or a 5 (radix 10) when at least two
 //     stages remain, and for complex64 into a 9 (radix 18, N = 162);
-//   - 60 = 6 x 10 and 96 = 16 x 6; for complex64 also 100 = 10 x 10 and 160 = 16 x 10.
+//   - 60 = 6 x 10 and 96 = 16 x 6; for complex64 also 100 = 10 x 10, 108 = 12 x 9, 120 = 8 x 15
+//     and 160 = 16 x 10.
 // The complex64-only merges ran 5-13% faster in complex64 and 3-8% slower in complex128.
 __host__ __device__ constexpr RPlan make_rplan(int N, bool dbl) {
   RPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
@@ -72,8 +73,15 @@ __host__ __device__ constexpr RPlan make_rplan(int N, bool dbl) {
   while (m % 5 == 0) { m /= 5; ++c; }
   if (a == 2 && b == 1 && c == 1) { p.r[p.n++] = 6; p.r[p.n++] = 10; return p; }
   if (a == 5 && b == 1 && c == 0) { p.r[p.n++] = 16; p.r[p.n++] = 6; return p; }
-  if (!dbl && a == 2 && b == 0 && c == 2) { p.r[p.n++] = 10; p.r[p.n++] = 10; return p; }
-  if (!dbl && a == 5 && b == 0 && c == 1) { p.r[p.n++] = 16; p.r[p.n++] = 10; return p; }
+  if (!dbl) {
+    // complex64: two stages with the composite radices 10, 12, 15 (measured faster; 150 = 15 x 10,
+    // 180 = 20 x 9, 192 = 16 x 12, 200 = 20 x 10 and 216 = 24 x 9 were 3-17% slower, 240 = 16 x 15
+    // no faster, so those keep three stages)
+    struct Two { int n, r0, r1; };
+    const Two two[] = {{100, 10, 10}, {160, 16, 10}, {108, 12, 9}, {120, 8, 15}};
+    for (const Two &t : two)
+      if (t.n == N) { p.r[p.n++] = t.r0; p.r[p.n++] = t.r1; return p; }
+  }
   int nines = b / 2, threes = b % 2, fives = c;
   const bool merge2 = a == 1 && (threes || fives || !dbl) && nines + threes + fives >= 2;
   const int twos[9][2] = {{0, 0}, {2, 0}, {4, 0}, {8, 0}, {16, 0}, {8, 4}, {8, 8}, {16, 8}, {16, 16}};

@@ -155,8 +155,8 @@ template <bool INV, typename V> struct Dft<5, INV, V> {
   }
 };
 
-// x * e^{-+ 2 pi i m / NN} for NN = 6, 9, 10, 18 or 25 and a compile-time m (forward sign -,
-// inverse +).
+// x * e^{-+ 2 pi i m / NN} for NN = 6, 9, 10, 12, 15, 18 or 25 and a compile-time m (forward
+// sign -, inverse +).
 // The tables hold cos and sin of 2 pi m / NN to 21 digits, with the symmetries
 // cos(2 pi (NN - m)/NN) = cos(2 pi m/NN), sin(2 pi (NN - m)/NN) = -sin(2 pi m/NN) exact.
 template <int M, int NN, bool INV, typename V>
@@ -197,6 +197,16 @@ __device__ __forceinline__ V rot_root(V a) {
                                  -0.642787609686539326323, -0.342020143325668733044};
       cm = cs[m];
       sm = sn[m];
+    } else if constexpr (NN == 12) {
+      constexpr double cs[12] = {1.0, 0.866025403784438646764, 0.5, 0.0, -0.5, -0.866025403784438646764, -1.0, -0.866025403784438646764, -0.5, 0.0, 0.5, 0.866025403784438646764};
+      constexpr double sn[12] = {0.0, 0.5, 0.866025403784438646764, 1.0, 0.866025403784438646764, 0.5, 0.0, -0.5, -0.866025403784438646764, -1.0, -0.866025403784438646764, -0.5};
+      cm = cs[m];
+      sm = sn[m];
+    } else if constexpr (NN == 15) {
+      constexpr double cs[15] = {1.0, 0.913545457642600895502, 0.669130606358858213826, 0.309016994374947424102, -0.1045284632676534714, -0.5, -0.809016994374947424102, -0.978147600733805637929, -0.978147600733805637929, -0.809016994374947424102, -0.5, -0.1045284632676534714, 0.309016994374947424102, 0.669130606358858213826, 0.913545457642600895502};
+      constexpr double sn[15] = {0.0, 0.406736643075800207754, 0.743144825477394235015, 0.951056516295153572116, 0.994521895368273336923, 0.866025403784438646764, 0.587785252292473129169, 0.207911690817759337102, -0.207911690817759337102, -0.587785252292473129169, -0.866025403784438646764, -0.994521895368273336923, -0.951056516295153572116, -0.743144825477394235015, -0.406736643075800207754};
+      cm = cs[m];
+      sm = sn[m];
     } else if constexpr (NN == 9) {
       constexpr double cs[9] = {1.0, 0.766044443118978035202, 0.173648177666930348852, -0.5,
                                 -0.939692620785908384054, -0.939692620785908384054, -0.5,
@@ -207,7 +217,7 @@ __device__ __forceinline__ V rot_root(V a) {
       cm = cs[m];
       sm = sn[m];
     } else {
-      static_assert(NN == 25, "roots of unity of order 6, 9, 10, 18 or 25");
+      static_assert(NN == 25, "roots of unity of order 6, 9, 10, 12, 15, 18 or 25");
       constexpr double cs[25] = {
           1.0, 0.968583161128631119490, 0.876306680043863587308, 0.728968627421411523147,
           0.535826794978996618271, 0.309016994374947424102, 0.062790519529313376076, -0.187381314585724630543,
@@ -321,6 +331,45 @@ template <bool INV, typename V> struct Dft<10, INV, V> {
 };
 template <bool INV, typename V> struct Dft<18, INV, V> {
   static __device__ __forceinline__ void run(V *v) { dft_split2<9, INV, V>(v); }
+};
+
+// Radix A B (A, B small): DFT_A over n1 of x[B n1 + n2], twiddle w_{AB}^{n2 k1}, DFT_B over
+// n2 -> X[k1 + A k2].  Used for the two-stage complex64 plans of sizes with several small
+// factors (radices 12 = 4 x 3 and 15 = 3 x 5).
+template <int A, int B, bool INV, typename V, int N2, int K1>
+__device__ __forceinline__ void splitab_twiddle(V (&t)[A], V (&y)[A][B]) {
+  if constexpr (K1 < A) {
+    y[K1][N2] = rot_root<N2 * K1, A * B, INV>(t[K1]);
+    splitab_twiddle<A, B, INV, V, N2, K1 + 1>(t, y);
+  }
+}
+template <int A, int B, bool INV, typename V, int N2 = 0>
+__device__ __forceinline__ void splitab_cols(V *v, V (&y)[A][B]) {
+  if constexpr (N2 < B) {
+    V t[A];
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) t[n1] = v[B * n1 + N2];
+    Dft<A, INV, V>::run(t);
+    splitab_twiddle<A, B, INV, V, N2, 0>(t, y);
+    splitab_cols<A, B, INV, V, N2 + 1>(v, y);
+  }
+}
+template <int A, int B, bool INV, typename V>
+__device__ __forceinline__ void dft_splitab(V *v) {
+  V y[A][B];
+  splitab_cols<A, B, INV, V>(v, y);
+#pragma unroll
+  for (int k1 = 0; k1 < A; ++k1) {
+    Dft<B, INV, V>::run(y[k1]);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = y[k1][k2];
+  }
+}
+template <bool INV, typename V> struct Dft<12, INV, V> {
+  static __device__ __forceinline__ void run(V *v) { dft_splitab<4, 3, INV, V>(v); }
+};
+template <bool INV, typename V> struct Dft<15, INV, V> {
+  static __device__ __forceinline__ void run(V *v) { dft_splitab<3, 5, INV, V>(v); }
 };
 
 // ---------------------------------------------------------- line geometry
