@@ -39,15 +39,17 @@ def parse():
     ap.add_argument("--no-host-io", action="store_true", help="skip the PCIe-inclusive solve after the timed region")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="ho128",
-                    choices=["ho128", "ab128", "coulomb", "batch64", "serve", "dft16"],
+                    choices=["ho128", "ab128", "coulomb", "rel256", "batch64", "serve", "dft16"],
                     help="ho128: the headline 128^3 workload; ab128: the same problem with H_K^(2) "
                          "stepped by the A/B update; coulomb: the Coulomb validation workload at 128^3; "
+                         "rel256: 256^3 relativistic Cornell solve with parity sectors and complex V; "
                          "batch64: 64 uneven Cornell solves in one batch; "
                          "serve: Poisson-arrival serving trace; "
                          "dft16: a batched 16-point DFT stage on the vector ALUs vs FP32 MFMA")
     ap.add_argument("--requests", type=int, default=100, help="serve: number of requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--batch-steps", type=int, default=5000, help="batch64: imaginary-time steps")
+    ap.add_argument("--rel-steps", type=int, default=1000, help="rel256: imaginary-time steps per solve")
     return ap.parse_args()
 
 
@@ -221,6 +223,23 @@ def bench_dft16(args):
     }
 
 
+def bench_rel256(args):
+    """256^3 with H_K^(3) = sqrt(p^2 + m^2) - m, Cornell V (alpha 0.4, sigma 0.2, m 1.5, a 0.05,
+    r floored at a/2) plus a seeded imaginary part, three states in the sectors (P+, P+, P^-_{p3}),
+    complex64 states with FP64 reductions: the row + three column pass schedule (a 256^2 plane
+    does not fit LDS), parity projection every 50 steps."""
+    import synthetic as S
+    p = S.config3()
+    p.steps = args.rel_steps
+    out = bench_problem(args, p, "Cornell 256^3, a=0.05, m=1.5, H_K^(3), complex V, sectors P+,P+,P-_p3, "
+                                 "%d steps, complex64 states, FP64 reductions" % p.steps)
+    # algorithmic bytes: read and write psi (8 + 8 B) and the complex potential factor (8 B) per
+    # site-update; the four passes move 24 + 3 x 16 = 72 B per site-update
+    out["path_roofline"] = {"bytes_per_su": 24, "pass_bytes_per_su": 72,
+                            "R_alg": round(out["value"] * 24 / (PEAK_HBM_GBS * 1e9), 4)}
+    return out
+
+
 def bench_serve(args):
     """Poisson serving trace: continuous batching in complex64 vs the plain FP64 single-solve path."""
     import numpy as np
@@ -383,6 +402,9 @@ def main():
         return
     if args.workload == "coulomb":
         print(json.dumps(bench_coulomb(args)), flush=True)
+        return
+    if args.workload == "rel256":
+        print(json.dumps(bench_rel256(args)), flush=True)
         return
     if args.workload == "dft16":
         print(json.dumps(bench_dft16(args)), flush=True)
