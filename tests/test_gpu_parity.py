@@ -123,6 +123,11 @@ ROW_CASES = [
     # tiles of 64 rows over 400-row states, complex potential
     ("rowcol_rel_cornell20_cV_c64", small(S.K_REL, 20, 0, S.V_CORNELL, (0.4, 0.2, 0.025), a=0.05, m=1.5,
                                           vgrid_seed=33, K=7, dt=0.05 / 8), 30),
+    # N^2 a multiple of the tile height: whole tiles per state, so consecutive blocks take the
+    # same rows of successive states (complex potential, then a real one in complex128)
+    ("rowcol_rel_cornell32_cV_c64", small(S.K_REL, 32, 0, S.V_CORNELL, (0.4, 0.2, 0.025), a=0.05, m=1.5,
+                                          vgrid_seed=35, K=7, dt=0.05 / 8), 30),
+    ("rowcol_p2_ho32_c128", small(S.K_NR_P2, 32, 1, K=7), 30),
 ]
 
 
