@@ -350,6 +350,30 @@ __device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, c
   constexpr int M = PL.n - 1;
   constexpr size_t N3 = (size_t)N * N * N;
   const C<T> zero = mkc<T>(0, 0);
+  // complex64: the potential factors of the fused middle stage are fetched before the first
+  // stage, so that their latency overlaps the inverse transform (at most one largest-radix
+  // butterfly's worth of values per lane; complex128 keeps its registers for the transform)
+  constexpr bool PRE = !AB && sizeof(T) == 4;
+  using SMID = SG<Rows, N, PL.r[M], NT>;
+  C<T> hq[PRE ? SMID::CAPQ : 1][PRE ? PL.r[M] : 1];
+  if constexpr (PRE) {
+    const bool vc = d.vcomplex != 0;
+#pragma unroll
+    for (int q = 0; q < SMID::CAPQ; ++q) {
+      if (SMID::active(q)) {
+        int j, b;
+        SMID::jb(q, j, b);
+#pragma unroll
+        for (int r = 0; r < PL.r[M]; ++r) {
+          hq[q][r] = zero;
+          if (b < nrows) {
+            const size_t s = row_site<T, N>(voff0, (size_t)b * N + j + r * SMID::NR);
+            hq[q][r] = vc ? ((const C<T> *)d.h2fac)[s] : mkc<T>(((const T *)d.h2fac)[s], 0);
+          }
+        }
+      }
+    }
+  }
   {
     constexpr int R = PL.r[0];
     C<T> v[SG<Rows, N, R, NT>::CAPQ][R];
@@ -379,6 +403,8 @@ __device__ __forceinline__ void row_steady(C<T> *buf, const C<T> *tw, C<T> *g, c
               const C<T> y = ab_combine<T>(gp[o], v[q][r], d, row_site<T, N>(voff0, o));
               gp[o] = y;
               v[q][r] = y;
+            } else if constexpr (PRE) {
+              v[q][r] = d.vcomplex ? cmul(v[q][r], hq[q][r]) : cscale(v[q][r], hq[q][r].x);
             } else {
               v[q][r] = vmul_t<T>(v[q][r], d.h2fac, d.vcomplex, row_site<T, N>(voff0, (size_t)b * N + j + r * SS::NR));
             }
