@@ -1,16 +1,19 @@
 """Benchmark: lattice site-updates/s of the imaginary-time evolution on one MI355X.
 
-Workload (one bench step): the harmonic-oscillator problem on a 128^3 lattice
-(a = 0.25, m = 1, V = r^2/2 centred on the lattice, 3 states from seeded
-Gaussian noise, dt = a^2/8, 5000 steps, orthonormalisation every 50 steps,
-complex64 states with FP64 reductions), solved twice: with the 7-point FDTD
-kinetic term H_K^(0) and with the 4 sin^2(k/2) FFT kinetic term H_K^(2), each
-to its three lowest energies.  The seeded initial states are resident in HBM
-before the timed region; each step copies them in on the device, evolves, and
-reads back the energies.
+Default workload (one bench step = one whole solve): the relativistic Cornell
+problem on a 256^3 periodic lattice (H_K^(3) = sqrt(p^2 + m^2) - m, m = 1.5,
+a = 0.05, V = -0.4/r_f + 0.2 r_f with r_f = max(r, a/2), plus a seeded
+imaginary part U(0, 0.01) drawn once per reflection orbit), 3 states in the
+parity sectors (P+, P+, P-_p3), dt = a/8, 10000 steps, orthonormalisation and
+parity projection every 50 steps, complex64 states with FP64 reductions, to its
+three lowest complex energies.  The seeded initial states are resident in HBM
+before the timed region; each bench step copies them in on the device, evolves
+and reads back the energies.
 
-Prints one JSON line.  value = site-updates/s = 2 solves x 3 states x 128^3
-sites x 5000 steps / (seconds per bench step).
+Prints one JSON line.  value = site-updates/s = 3 states x 256^3 sites x 10000
+steps / (seconds per bench step).  Other workloads: --workload ho128 (the
+harmonic oscillator at 128^3 with FDTD and H_K^(2)), ab128, coulomb, batch64,
+serve, dft16.
 """
 import argparse
 import hashlib
@@ -33,23 +36,23 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--imag-steps", type=int, default=5000, help="imaginary-time steps per solve")
+    ap.add_argument("--imag-steps", type=int, default=None,
+                    help="imaginary-time steps per solve (default: 10000 for rel256, 5000 otherwise)")
     ap.add_argument("--timing-every", type=int, default=8, help="time one launch in this many")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-host-io", action="store_true", help="skip the PCIe-inclusive solve after the timed region")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="ho128",
+    ap.add_argument("--workload", default="rel256",
                     choices=["ho128", "ab128", "coulomb", "rel256", "batch64", "serve", "dft16"],
-                    help="ho128: the headline 128^3 workload; ab128: the same problem with H_K^(2) "
+                    help="rel256 (default): 256^3 relativistic Cornell solve with parity sectors and complex V; "
+                         "ho128: the 128^3 harmonic oscillator with FDTD and H_K^(2); ab128: the same problem with H_K^(2) "
                          "stepped by the A/B update; coulomb: the Coulomb validation workload at 128^3; "
-                         "rel256: 256^3 relativistic Cornell solve with parity sectors and complex V; "
                          "batch64: 64 uneven Cornell solves in one batch; "
                          "serve: Poisson-arrival serving trace; "
                          "dft16: a batched 16-point DFT stage on the vector ALUs vs FP32 MFMA")
     ap.add_argument("--requests", type=int, default=100, help="serve: number of requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--batch-steps", type=int, default=5000, help="batch64: imaginary-time steps")
-    ap.add_argument("--rel-steps", type=int, default=1000, help="rel256: imaginary-time steps per solve")
     return ap.parse_args()
 
 
@@ -115,7 +118,8 @@ def roofline_of(solvers):
 
 
 def bench_problem(args, p, workload, extra=None):
-    """Site-updates/s of one solve of ``p`` (states resident on the device before timing)."""
+    """Site-updates/s of one solve of ``p`` per bench step (states resident on the device before
+    timing); per-solve latency; launch-timed roofline of the dominant pass class."""
     import numpy as np
     import torch
     from paper_2211_10185_amd.solver import Solver
@@ -133,23 +137,30 @@ def bench_problem(args, p, workload, extra=None):
     for _ in range(args.warmup):
         solve()
     torch.cuda.synchronize()
+    lat = []
     t0 = time.perf_counter()
     for st in range(args.steps):
         if st == args.steps - 1:
             s.enable_kernel_timing(args.timing_every)   # last step: each timed launch runs alone
-        E = solve()
+        t1 = time.perf_counter()
+        E = solve()                                     # energies() synchronises
+        lat.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    _, roof = roofline_of([s])
-    s.close()
+    dom, roof = roofline_of([s])
+    s.enable_kernel_timing(0)
     value = k * N ** 3 * p.steps * args.steps / el
+    lat_ms = sorted(1e3 * x for x in lat)
     out = {"metric": "lattice site-updates/s", "value": value, "unit": "site-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic", "config": {"workload": workload, "N": N, "states": k, "imag_steps": p.steps},
-           "energies": [round(e.real, 9) for e in E], "roofline": roof}
+           "solves_per_s": args.steps / el,
+           "solve_latency_ms": {"p50": lat_ms[len(lat_ms) // 2],
+                                "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))]},
+           "energies": [[round(e.real, 9), round(e.imag, 9)] for e in E], "roofline": roof}
     out.update(extra or {})
-    return out
+    return out, s, dom
 
 
 def bench_ab(args):
@@ -157,12 +168,15 @@ def bench_ab(args):
     import synthetic as S
     p = S.config2(S.K_NR_SIN2)
     p.scheme = S.SCHEME_AB
-    p.steps = args.imag_steps
-    out = bench_problem(args, p, "harmonic oscillator 128^3, a=0.25, m=1, 3 states, dt=a^2/8, %d steps, "
-                                 "FFT H_K^(2) with the A/B update, complex64 states, FP64 reductions" % p.steps)
-    # pass model: column pass 16 B/SU + combine pass (alt, psi, V in; psi, alt out) 36 B/SU
-    out["path_roofline"] = {"bytes_per_su": 20, "pass_bytes_per_su": 52,
-                            "R_alg": round(out["value"] * 20 / (PEAK_HBM_GBS * 1e9), 4)}
+    p.steps = args.imag_steps or 5000
+    out, s, _ = bench_problem(args, p, "harmonic oscillator 128^3, a=0.25, m=1, 3 states, dt=a^2/8, %d steps, "
+                                       "FFT H_K^(2) with the A/B update, complex64 states, FP64 reductions" % p.steps)
+    s.close()
+    # algorithmic: psi in and out (16 B) and the real FP32 factor shared by the 3 states (4/3 B);
+    # pass model: column pass 16 B/SU + combine pass (alt, psi in; psi, alt out; V) 32 + 4/3 B/SU
+    bsu = 16 + 4 / 3
+    out["path_roofline"] = {"bytes_per_su": round(bsu, 3), "pass_bytes_per_su": round(48 + 4 / 3, 3),
+                            "R_alg": round(out["value"] * bsu / (PEAK_HBM_GBS * 1e9), 4)}
     return out
 
 
@@ -172,10 +186,11 @@ def bench_coulomb(args):
     import oracle as O
     import synthetic as S
     p = S.coulomb_problem(S.K_NR_SIN2, N=128, a=0.12, alpha=1.0)
-    out = bench_problem(args, p, "Coulomb 128^3, a=0.12 fm, m=0.3 GeV, alpha=1, H_K^(2), sectors P+,P+,P-_p3, "
-                                 "%d steps (tau=80 fm), complex64 states, FP64 reductions" % p.steps)
+    out, s, _ = bench_problem(args, p, "Coulomb 128^3, a=0.12 fm, m=0.3 GeV, alpha=1, H_K^(2), sectors P+,P+,P-_p3, "
+                                       "%d steps (tau=80 fm), complex64 states, FP64 reductions" % p.steps)
+    s.close()
     th = [O.hydrogen_level(n, p.m, 1.0) for n in (1, 2, 2)]
-    out["hydrogen_rel_error"] = [round((e - t) / abs(t), 5) for e, t in zip(out["energies"], th)]
+    out["hydrogen_rel_error"] = [round((e[0] - t) / abs(t), 5) for e, t in zip(out["energies"], th)]
     return out
 
 
@@ -226,17 +241,38 @@ def bench_dft16(args):
 def bench_rel256(args):
     """256^3 with H_K^(3) = sqrt(p^2 + m^2) - m, Cornell V (alpha 0.4, sigma 0.2, m 1.5, a 0.05,
     r floored at a/2) plus a seeded imaginary part, three states in the sectors (P+, P+, P^-_{p3}),
-    complex64 states with FP64 reductions: the row + three column pass schedule (a 256^2 plane
-    does not fit LDS), parity projection every 50 steps."""
+    complex64 states with FP64 reductions, parity projection and orthonormalisation every 50
+    steps; one whole solve per bench step."""
+    import torch
     import synthetic as S
     p = S.config3()
-    p.steps = args.rel_steps
-    out = bench_problem(args, p, "Cornell 256^3, a=0.05, m=1.5, H_K^(3), complex V, sectors P+,P+,P-_p3, "
-                                 "%d steps, complex64 states, FP64 reductions" % p.steps)
-    # algorithmic bytes: read and write psi (8 + 8 B) and the complex potential factor (8 B) per
-    # site-update; the four passes move 24 + 3 x 16 = 72 B per site-update
-    out["path_roofline"] = {"bytes_per_su": 24, "pass_bytes_per_su": 72,
-                            "R_alg": round(out["value"] * 24 / (PEAK_HBM_GBS * 1e9), 4)}
+    p.steps = args.imag_steps or 10000
+    out, s, dom = bench_problem(args, p, "relativistic Cornell 256^3, a=0.05, m=1.5, H_K^(3) (rest mass removed), "
+                                         "V=-0.4/r+0.2r (r floored at a/2) + i U(0,0.01) per reflection orbit, "
+                                         "3 states in sectors P+,P+,P-_p3, dt=a/8, %d steps, complex64 states, "
+                                         "FP64 reductions" % p.steps)
+    out["config"]["reductions"] = "f64"
+    out["roofline"]["traffic"] = traffic_from_profiles("traffic_rel256.json", CLASS_NAMES[dom])
+    # algorithmic bytes per site-update: psi in and out (8 + 8 B) and the complex FP32 potential
+    # factor, which the 3 states share, read once per step (8/3 B)
+    bsu = 16 + 8 / 3
+    out["path_roofline"] = {"bytes_per_su": round(bsu, 3), "R_alg": round(out["value"] * bsu / (PEAK_HBM_GBS * 1e9), 4),
+                            "copy_ceiling_GBps": copy_ceiling_gbs()}
+    out["device"] = device_record()
+    if not args.no_host_io:
+        # outside the timed region: the same solve with the states handed over in host memory
+        # (complex128 upload, complex128 readback of states and energies): the PCIe-inclusive rate
+        init = p.init_states()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_states(init)
+        s.evolve(p.steps, p.dt)
+        s.states()
+        t_host = time.perf_counter() - t0
+        out["host_io"] = {"value": p.k * p.N ** 3 * p.steps / t_host, "unit": "site-updates/s",
+                          "note": "states uploaded from and read back to host memory (complex128) around the solve"}
+    s.close()
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline_split(p, args.cpu_seconds)
     return out
 
 
@@ -288,9 +324,9 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(cls_name):
+def traffic_from_profiles(fname, cls_name):
     """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernels."""
-    path = os.path.join(ROOT, "profiles", "traffic_ho128.json")
+    path = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(path):
         return None
     try:
@@ -377,12 +413,33 @@ def cpu_baseline(p_fdtd, p_fft, seconds):
                       "orthonormalisation excluded" % (res[p_fdtd.label], res[p_fft.label], O.WORKERS, total_t)}
 
 
+def cpu_baseline_split(p, seconds):
+    """The oracle, untuned, on a bounded sample of the same solve: FP64 split steps of all k states
+    for about ``seconds`` of wall time (the factors exp(-dt V/2), exp(-dt T) computed once, as the
+    oracle's own evolution loop does)."""
+    import oracle as O
+    V = O.problem_potential(p)
+    sectors = list(p.sectors) if p.sectors else [0] * p.k
+    st = O.prepare(p.init_states(), sectors, True)
+    T = O.kinetic_symbol(p.kinetic, p.N, p.a, p.m)
+    fac = O.split_factors(T, V, p.dt)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        st = [O.step_split(x, T, V, p.dt, fac) for x in st]
+        n += 1
+    el = time.perf_counter() - t0
+    return {"value": n * p.k * p.N ** 3 / el, "unit": "site-updates/s", "cores": O.WORKERS, "kind": "oracle",
+            "sample": "FP64 numpy/scipy oracle: %d split steps of the same %d-state %d^3 problem (%d FFT threads, "
+                      "%.0f s wall); orthonormalisation and setup excluded" % (n, p.k, p.N, O.WORKERS, el)}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
-              "(one lattice per GPU; sharding is described in DESIGN.md)", file=sys.stderr)
+              "(one lattice or one batch of lattices per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -410,10 +467,11 @@ def main():
         print(json.dumps(bench_dft16(args)), flush=True)
         return
     dev = torch.device("cuda:0")
+    imag = args.imag_steps or 5000
     p_fdtd = S.config2(S.K_FDTD)
     p_fft = S.config2(S.K_NR_SIN2)
     for p in (p_fdtd, p_fft):
-        p.steps = args.imag_steps
+        p.steps = imag
     N, k = p_fft.N, p_fft.k
     init = p_fft.init_states()        # same seed for both forms
     init_dev = torch.from_numpy(init.astype(np.complex64)).to(dev)
@@ -453,7 +511,7 @@ def main():
     elapsed = time.perf_counter() - t0
 
     ms_per_step = 1e3 * elapsed / args.steps
-    su_per_step = 2 * k * N ** 3 * args.imag_steps
+    su_per_step = 2 * k * N ** 3 * imag
     value = su_per_step / (elapsed / args.steps)
 
     # dominant kernel class by total time in the timed region
@@ -470,7 +528,7 @@ def main():
     dom = max(stats, key=lambda c: stats[c][3])
     cnt, mean_ms, bytes_per_launch, _ = stats[dom]
     achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(CLASS_NAMES[dom])
+    traffic = traffic_from_profiles("traffic_ho128.json", CLASS_NAMES[dom])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
             "kernel": KERNEL_SYMBOLS[dom], "mean_launch_ms": round(mean_ms, 5),
@@ -487,16 +545,18 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "harmonic oscillator 128^3, a=0.25, m=1, 3 states, dt=a^2/8, %d steps, "
-                               "FDTD H_K^(0) + FFT H_K^(2), complex64 states, FP64 reductions" % args.imag_steps,
-                   "N": N, "states": k, "imag_steps": args.imag_steps, "solves_per_step": 2,
+                               "FDTD H_K^(0) + FFT H_K^(2), complex64 states, FP64 reductions" % imag,
+                   "N": N, "states": k, "imag_steps": imag, "solves_per_step": 2,
                    "reductions": "f64"},
         "solves_per_s": 2 * args.steps / elapsed,
         "solve_latency_ms": {"p50": lat_ms[len(lat_ms) // 2], "p99": lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))]},
         "energies": {"fdtd": [round(e.real, 9) for e in energies[0]], "sin2": [round(e.real, 9) for e in energies[1]]},
         "roofline": roof,
-        # whole path: algorithmic bytes (20 B per site-update: read + write a complex64 site, read
-        # the real FP32 potential factor) at the measured rate, against the peak and a measured copy
-        "path_roofline": {"bytes_per_su": 20, "R_alg": round(value * 20 / (PEAK_HBM_GBS * 1e9), 4),
+        # whole path: algorithmic bytes (16 + 4/3 B per site-update: read + write a complex64 site,
+        # read the real FP32 potential factor that the 3 states share once per step) at the
+        # measured rate, against the peak and a measured copy
+        "path_roofline": {"bytes_per_su": round(16 + 4 / 3, 3),
+                          "R_alg": round(value * (16 + 4 / 3) / (PEAK_HBM_GBS * 1e9), 4),
                           "copy_ceiling_GBps": copy_ceiling_gbs(),
                           "copy_ceiling_cache_resident_GBps": copy_ceiling_gbs(48 << 20, reps=40)},
         "device": device_record(),

@@ -82,7 +82,10 @@ typedef enum {
 /* Parity sectors (Sec. 3).  Reflection R_l maps site i_l to N - i_l
  * (mod N on the periodic lattice; onto the wall, where psi = 0, for FDTD).
  *   P^+ = (1 + R)/2, P^- = (1 - R)/2 with R = R_1 R_2 R_3,
- *   P^-_{p_k} = (1 + R_i R_j)(1 - R_k)/4, {i, j, k} = {1, 2, 3}. */
+ *   P^-_{p_k} = (1 + R_i R_j)(1 - R_k)/4, {i, j, k} = {1, 2, 3}.
+ * On the walled lattice a site with some i_l = 0 mirrors onto the wall, so a state of
+ * definite parity vanishes there: the projection sets those sites to zero, which keeps
+ * the projectors idempotent. */
 typedef enum {
   QFDTD_S_NONE = 0,
   QFDTD_S_PLUS = 1,
@@ -224,7 +227,8 @@ qfdtd_status qfdtd_write_potential_ascii(const char *path, int32_t N, const doub
  * pair of HIP events on its stream around every sampled launch, per kernel class.
  * qfdtd_kernel_stats returns, for class `cls` (0 plane, 1 row, 2 column, 3 stencil,
  * 4 measurement), the number of timed launches, their mean duration in ms and the
- * algorithmic bytes one launch of that class moves (read once + written once).
+ * algorithmic bytes one launch of that class moves: every state read once and written once,
+ * plus the per-site potential factor, shared by the k states of a solve, read once.
  * While timing is enabled the states of an FFT solve are not split over internal
  * streams, so timed launches never overlap other kernels of the context.  every <= 0
  * disables timing.  Synchronises the stream. */

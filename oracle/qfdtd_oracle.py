@@ -44,6 +44,9 @@ Readings of the paper that this oracle takes (the text is silent or ambiguous):
   after the last step.
 * P^-_{p_k} uses the idempotent normalisation 1/4 (the printed 1/2 only
   rescales, which normalisation removes).
+* On the walled lattice a site with some i_l = 0 has its mirror image on the
+  wall, so a state of definite parity vanishes there; the projectors set those
+  sites to zero (which keeps them idempotent).
 * Energies are Rayleigh quotients <psi_i|H|psi_i> of the normalised states.
 """
 from __future__ import annotations
@@ -212,10 +215,19 @@ def hydrogen_1s_momentum(p: np.ndarray, m: float, alpha: float) -> np.ndarray:
 # one imaginary-time step
 # --------------------------------------------------------------------------
 
-def step_split(psi: np.ndarray, T: np.ndarray, V: np.ndarray, dt: float) -> np.ndarray:
-    """Symmetric split step  h IFFT[exp(-dt T) FFT[h psi]],  h = exp(-dt V / 2)."""
-    h = np.exp(-0.5 * dt * V)
-    return h * ifft3(np.exp(-dt * T) * fft3(h * psi))
+def split_factors(T: np.ndarray, V: np.ndarray, dt: float):
+    """The two factors of the symmetric split step: h = exp(-dt V / 2) and exp(-dt T)."""
+    return np.exp(-0.5 * dt * V), np.exp(-dt * T)
+
+
+def step_split(psi: np.ndarray, T: np.ndarray, V: np.ndarray, dt: float,
+               factors=None) -> np.ndarray:
+    """Symmetric split step  h IFFT[exp(-dt T) FFT[h psi]],  h = exp(-dt V / 2).
+
+    ``factors`` may carry ``split_factors(T, V, dt)`` computed once for many steps; the
+    values are the same either way."""
+    h, eT = split_factors(T, V, dt) if factors is None else factors
+    return h * ifft3(eT * fft3(h * psi))
 
 
 def step_ab_fft(psi: np.ndarray, T: np.ndarray, V: np.ndarray, dt: float) -> np.ndarray:
@@ -288,16 +300,28 @@ def reflect(psi: np.ndarray, axes: Sequence[int], periodic: bool = True) -> np.n
 
 
 def parity_project(psi: np.ndarray, sector: int, periodic: bool = True) -> np.ndarray:
-    """P^+ = (1 + R)/2,  P^- = (1 - R)/2,  P^-_{p_k} = (1 + R_{other two})(1 - R_k)/4."""
+    """P^+ = (1 + R)/2,  P^- = (1 - R)/2,  P^-_{p_k} = (1 + R_{other two})(1 - R_k)/4.
+
+    On the walled lattice only the sites with every i_l >= 1 have their mirror image inside
+    the box (the mirror of i_l = 0 is the wall, where psi = 0), so a state of definite parity
+    vanishes wherever some i_l = 0; the projection sets those sites to zero.  This keeps the
+    walled projectors idempotent and the sectors orthogonal (Sec. 3 uses them as projectors).
+    """
     if sector == S_NONE:
         return psi
     if sector in (S_PLUS, S_MINUS):
         sgn = 1.0 if sector == S_PLUS else -1.0
-        return 0.5 * (psi + sgn * reflect(psi, (0, 1, 2), periodic))
-    kax = sector - S_PK1
-    others = tuple(ax for ax in (0, 1, 2) if ax != kax)
-    return 0.25 * (psi + reflect(psi, others, periodic) - reflect(psi, (kax,), periodic)
-                   - reflect(psi, (0, 1, 2), periodic))
+        out = 0.5 * (psi + sgn * reflect(psi, (0, 1, 2), periodic))
+    else:
+        kax = sector - S_PK1
+        others = tuple(ax for ax in (0, 1, 2) if ax != kax)
+        out = 0.25 * (psi + reflect(psi, others, periodic) - reflect(psi, (kax,), periodic)
+                      - reflect(psi, (0, 1, 2), periodic))
+    if not periodic:
+        out[0, :, :] = 0.0
+        out[:, 0, :] = 0.0
+        out[:, :, 0] = 0.0
+    return out
 
 
 def inner(x: np.ndarray, y: np.ndarray) -> complex:
@@ -341,25 +365,29 @@ def project_and_orthonormalise(states, sectors, periodic):
 
 def evolve(states: List[np.ndarray], kind: int, a: float, m: float, V: np.ndarray,
            dt: float, steps: int, K: int, sectors: Sequence[int],
-           trace: Optional[list] = None, scheme: int = SCHEME_SPLIT) -> List[np.ndarray]:
+           trace: Optional[list] = None, scheme: int = SCHEME_SPLIT,
+           map_fn=map) -> List[np.ndarray]:
     """Run ``steps`` steps in chunks of K; project + orthonormalise after each chunk.
 
     ``states`` must already be projected and orthonormalised (see ``prepare``).
     If ``trace`` is a list, the energies after every chunk are appended to it.
     ``scheme`` selects the step of the FFT kinetic terms (split operator or A/B).
+    ``map_fn`` applies one step to every state; the states are independent between two
+    orthonormalisations, so a thread pool's ``map`` gives the same results as ``map``.
     """
     periodic = kind != K_FDTD
     T = kinetic_symbol(kind, states[0].shape[-1], a, m) if periodic else None
+    fac = split_factors(T, V, dt) if periodic and scheme == SCHEME_SPLIT else None
     done = 0
     while done < steps:
         n = min(K, steps - done)
         for _ in range(n):
             if periodic and scheme == SCHEME_AB:
-                states = [step_ab_fft(s, T, V, dt) for s in states]
+                states = list(map_fn(lambda s: step_ab_fft(s, T, V, dt), states))
             elif periodic:
-                states = [step_split(s, T, V, dt) for s in states]
+                states = list(map_fn(lambda s: step_split(s, T, V, dt, fac), states))
             else:
-                states = [step_fdtd(s, V, dt, a, m) for s in states]
+                states = list(map_fn(lambda s: step_fdtd(s, V, dt, a, m), states))
         done += n
         states = project_and_orthonormalise(states, sectors, periodic)
         if trace is not None:

@@ -497,6 +497,9 @@ __global__ void __launch_bounds__(RED_THREADS) k_parity(const LaunchList L) {
       else { r_oth = at(m1, m2, i3); r_k = at(i1, i2, m3); }
       out = cscale(csub(cadd(v, r_oth), cadd(r_k, all)), (T)0.25);
     }
+    // walled lattice: a site with some i_l = 0 mirrors onto the wall, so a state of definite
+    // parity vanishes there (the projector stays idempotent)
+    if (!periodic && (i1 == 0 || i2 == 0 || i3 == 0)) out = mkc<T>(0, 0);
     dst[gi] = out;
   }
 }

@@ -316,23 +316,26 @@ struct Entry {
 
 enum Fam { F_PLANE, F_ROW, F_COL, F_STENCIL, F_STENCIL2, F_PARITY, F_TO64, F_GRAM, F_APPLY, F_EPART, F_KPART, F_GFIN, F_EFIN };
 
-// algorithmic bytes moved by one member's share of a launch (for timing)
+// Algorithmic bytes moved by one member's share of a launch (for timing): every state is read
+// and written once, and the per-site potential factor, which all k states of the member share,
+// is read once per launch.
 double entry_bytes(const Entry &e, Fam f) {
   const qfdtd_ctx *c = e.c;
   const bool meas = e.which == 1;
   const int k = e.which >= 2 ? c->gk[e.which - 2] : c->k;
   const double n = (double)k * c->n3();
+  const double n3 = (double)c->n3();
   const double s = meas ? 16.0 : (double)c->csz();
   const double fsz = (c->vcomplex ? 2.0 : 1.0) * (meas ? 8.0 : (double)c->rsz());
   switch (f) {
     case F_PLANE:
     case F_ROW:
       // A/B combine: read alt and psi and V, write psi (and alt when the forward follows)
-      if (e.mode & M_COMB) return n * (3 * s + fsz + ((e.mode & M_FWD) ? s : 0.0));
-      return n * (2 * s + ((e.mode & (M_PRE | M_MID | M_POST)) ? fsz : 0.0));
+      if (e.mode & M_COMB) return n * (3 * s + ((e.mode & M_FWD) ? s : 0.0)) + n3 * fsz;
+      return n * 2 * s + ((e.mode & (M_PRE | M_MID | M_POST)) ? n3 * fsz : 0.0);
     case F_COL: return n * 2 * s;
-    case F_STENCIL: return n * (2 * s + fsz);
-    case F_STENCIL2: return 2 * n * (2 * s + fsz);    // two steps per launch
+    case F_STENCIL: return n * 2 * s + n3 * fsz;
+    case F_STENCIL2: return 2 * (n * 2 * s + n3 * fsz);    // two steps per launch
     default: return n * 2 * s;
   }
 }
@@ -405,7 +408,10 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
     L.n = (int)cnt;
     L.tile_start[cnt] = total;
     int cls = -1;
-    if (f == F_PLANE) cls = TC_PLANE;
+    bool meas_copy = false;     // transforms of the FP64 measurement copy count as measurement
+    for (size_t i = 0; i < cnt; ++i) meas_copy = meas_copy || es[base + i].which == 1;
+    if (meas_copy) cls = TC_MEAS;
+    else if (f == F_PLANE) cls = TC_PLANE;
     else if (f == F_ROW) cls = TC_ROW;
     else if (f == F_COL) cls = TC_COL;
     else if (f == F_STENCIL || f == F_STENCIL2) cls = TC_STENCIL;

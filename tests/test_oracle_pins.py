@@ -689,3 +689,73 @@ def test_snapshot_extraction_reaches_exact_levels_and_fails_in_fp32():
     j1f, v1f = O.stationary_point(E1f, r1f, floor32)
     assert 1e-4 < v1f - e1 < 2e-2, v1f - e1
     assert taus[j1f] < taus[j1]
+
+
+# ------------------------------------------------- walled parity, Coulomb, serving rule
+
+def test_walled_parity_projects_onto_the_symmetric_interior():
+    # On the walled lattice the sites 1..N-1 of every axis are symmetric about the origin site
+    # N/2; there R is the reversal of the interior block.  A brute-force projector built with
+    # np.flip on that block (and zero on the i_l = 0 planes) must equal the oracle's.
+    N = 8
+    psi = rnd((N, N, N), 21)
+    inner_blk = psi[1:, 1:, 1:]
+    flip_all = np.flip(inner_blk, axis=(0, 1, 2))
+    want = {O.S_PLUS: 0.5 * (inner_blk + flip_all), O.S_MINUS: 0.5 * (inner_blk - flip_all)}
+    for k in range(3):
+        oth = tuple(ax for ax in range(3) if ax != k)
+        want[O.S_PK1 + k] = 0.25 * (inner_blk + np.flip(inner_blk, axis=oth) - np.flip(inner_blk, axis=k) - flip_all)
+    for sec, w in want.items():
+        got = O.parity_project(psi, sec, periodic=False)
+        assert np.all(got[0] == 0) and np.all(got[:, 0] == 0) and np.all(got[:, :, 0] == 0)
+        np.testing.assert_allclose(got[1:, 1:, 1:], w, atol=1e-15)
+        # idempotent, and the sectors are orthogonal
+        np.testing.assert_allclose(O.parity_project(got, sec, periodic=False), got, atol=1e-15)
+    Pp = O.parity_project(psi, O.S_PLUS, periodic=False)
+    assert np.abs(O.parity_project(Pp, O.S_MINUS, periodic=False)).max() < 1e-15
+    for k in (O.S_PK1, O.S_PK2, O.S_PK3):
+        assert np.abs(O.parity_project(O.parity_project(psi, k, periodic=False), O.S_PLUS,
+                                       periodic=False)).max() < 1e-15
+    # P^+ + P^- is the identity on the interior
+    Pm = O.parity_project(psi, O.S_MINUS, periodic=False)
+    np.testing.assert_allclose((Pp + Pm)[1:, 1:, 1:], inner_blk, atol=1e-15)
+
+
+def test_coulomb_potential_floor_and_off_axis_value():
+    N, a, alpha = 16, 0.12, 0.7
+    x = O.coords(N, a)
+    c = N // 2
+    V = O.potential(N, a, O.V_COULOMB, (alpha, a / 2))
+    assert abs(V[c, c, c] - (-alpha / (a / 2))) < 1e-15          # r = 0 floored at a/2
+    assert abs(V[c, c, c + 1] - (-alpha / a)) < 1e-14              # nearest neighbour: r = a > a/2
+    r = math.sqrt(x[2] ** 2 + x[13] ** 2 + x[5] ** 2)
+    assert abs(V[2, 13, 5] - (-alpha / r)) < 1e-14
+    assert np.all(V.imag == 0) and V.real.max() < 0
+
+
+def test_serving_rule_stops_at_the_hand_counted_chunk():
+    # V = 0 on the periodic lattice with H_K^(2): a uniform mode u (T = 0) plus eps times a plane
+    # wave w along x3 (T1 = 4 sin^2(pi/N)/(2 m a^2)).  The split step multiplies w by exp(-dt T1)
+    # and leaves u, so after m chunks of K steps E0 = T1 q/(1 + q), q = eps^2 exp(-2 m K dt T1);
+    # the rule stops at the first chunk m >= 2 with |E0(m) - E0(m-1)| < tol.
+    N, a, m, dt, K, eps, tol = 8, 1.0, 1.0, 0.1, 10, 0.8, 1e-8
+    x3 = np.arange(N)
+    u = np.ones((N, N, N), complex)
+    w = np.exp(2j * np.pi * x3 / N)[None, None, :] * np.ones((N, N, 1))
+    T1 = 4 * math.sin(math.pi / N) ** 2 / (2 * m * a * a)
+    p = S.Problem(N=N, a=a, m=m, kinetic=O.K_NR_SIN2, vkind=S.V_GRID, grid=np.zeros((N, N, N)), k=1,
+                  dt=dt, steps=100000, measure_every=K, seed=1)
+    prev, chunk = None, 0
+    while True:
+        chunk += 1
+        q = eps ** 2 * math.exp(-2 * chunk * K * dt * T1)
+        e = T1 * q / (1 + q)
+        if prev is not None and abs(e - prev) < tol:
+            break
+        prev = e
+    res = O.solve_until_converged(p, tol=tol, init=(u + eps * w)[None])
+    assert res["steps"] == chunk * K
+    assert abs(res["energies"][0] - e) < 1e-13
+    # the cap stops a solve that never meets the tolerance
+    capped = O.solve_until_converged(p, tol=0.0, max_steps=5 * K, init=(u + eps * w)[None])
+    assert capped["steps"] == 5 * K
