@@ -27,8 +27,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-CLASS_NAMES = {0: "plane_pass", 1: "row_pass", 2: "column_pass", 3: "fdtd_stencil"}
-KERNEL_SYMBOLS = {0: "k_plane", 1: "k_row", 2: "k_col", 3: "k_stencil"}
+CLASS_NAMES = {0: "plane_pass", 1: "row_pass", 2: "column_pass", 3: "fdtd_stencil", 5: "slab_pass",
+               6: "pencil_pass"}
+KERNEL_SYMBOLS = {0: "k_plane", 1: "k_row", 2: "k_col", 3: "k_stencil", 5: "k_slab", 6: "k_pencil"}
+PASS_CLASSES = (0, 1, 2, 3, 5, 6)
 
 
 def parse():
@@ -50,6 +52,10 @@ def parse():
                          "batch64: 64 uneven Cornell solves in one batch; "
                          "serve: Poisson-arrival serving trace; "
                          "dft16: a batched 16-point DFT stage on the vector ALUs vs FP32 MFMA")
+    ap.add_argument("--split", choices=["auto", "on", "off"], default="auto",
+                    help="FFT solves: the split-x2 two-pass schedule where it exists (auto: the tuned choice)")
+    ap.add_argument("--split-variant", type=int, choices=[0, 1], default=None,
+                    help="split-x2 pencil tile: 0 = 4 x3 columns, 1 = 2 (default: the tuned choice)")
     ap.add_argument("--requests", type=int, default=100, help="serve: number of requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--batch-steps", type=int, default=5000, help="batch64: imaginary-time steps")
@@ -93,7 +99,7 @@ def bench_batch(args):
 def roofline_of(solvers):
     """Dominant pass class by total time (launch-attached HIP events), its algorithmic GB/s."""
     stats = {}
-    for cls in (0, 1, 2, 3):
+    for cls in PASS_CLASSES:
         cnt, tot_ms, tot_b = 0, 0.0, 0.0
         for s in solvers:
             n, mean_ms, b = s.kernel_stats(cls)
@@ -126,7 +132,10 @@ def bench_problem(args, p, workload, extra=None):
     from paper_2211_10185_amd import _lib
     N, k = p.N, p.k
     init_dev = torch.from_numpy(p.init_states().astype(np.complex64)).to("cuda")
-    s = Solver.from_problem(p)
+    kw = {} if args.split == "auto" else {"split": args.split == "on"}
+    if args.split_variant is not None:
+        kw["split_variant"] = args.split_variant
+    s = Solver.from_problem(p, **kw)
 
     def solve():
         for i in range(k):
@@ -252,6 +261,9 @@ def bench_rel256(args):
                                          "3 states in sectors P+,P+,P-_p3, dt=a/8, %d steps, complex64 states, "
                                          "FP64 reductions" % p.steps)
     out["config"]["reductions"] = "f64"
+    out["config"]["schedule"] = ("split-x2 (slab + pencil passes, %d-column pencil tiles)"
+                                 % (4 if s.schedule["split_variant"] == 0 else 2)
+                                 if s.schedule["split"] else "row + three column passes")
     out["roofline"]["traffic"] = traffic_from_profiles("traffic_rel256.json", CLASS_NAMES[dom])
     # algorithmic bytes per site-update: psi in and out (8 + 8 B) and the complex FP32 potential
     # factor, which the 3 states share, read once per step (8/3 B)
@@ -516,7 +528,7 @@ def main():
 
     # dominant kernel class by total time in the timed region
     stats = {}
-    for cls in (0, 1, 2, 3):
+    for cls in PASS_CLASSES:
         cnt, tot_ms, tot_b = 0, 0.0, 0.0
         for s in solvers:
             n, mean_ms, b = s.kernel_stats(cls)

@@ -135,6 +135,18 @@ typedef struct {
                                      so the results are bit-identical) and halves the memory
                                      traffic per step; a chunk of odd length ends with a
                                      single step. */
+#define QFDTD_F_SPLIT_X2 64u     /* FFT kinds, complex64, sizes with a split-x2 instantiation (N = 256):
+                                     the two-pass schedule.  The x2 transform is split four-step
+                                     style (N = N1 N2); a slab pass holds N1 rows of one x1 plane
+                                     and does the x3 transforms around the potential factor and
+                                     the stride-N2 part of x2, a pencil pass holds N2 consecutive
+                                     rows of a few x3 columns over all x1 and does the other part
+                                     of x2 and the x1 transforms around the kinetic factor.  Two
+                                     passes over the state per step instead of four (schedule
+                                     autotuning; ignored with QFDTD_F_AB_SCHEME). */
+#define QFDTD_F_SPLIT_NARROW 128u /* with QFDTD_F_SPLIT_X2: pencil tiles of 2 x3 columns instead of 4
+                                     (half the on-chip memory per tile, so two tiles share a
+                                     compute unit; schedule autotuning) */
 #define QFDTD_F_AB_SCHEME 8u      /* FFT kinds: step with the legacy update of H_K^(0) with the
                                      FFT kinetic term swapped in (Sec. 2, the update the paper
                                      keeps while changing H_K):  psi' = A psi - B dt H_K psi,
@@ -226,7 +238,7 @@ qfdtd_status qfdtd_write_potential_ascii(const char *path, int32_t N, const doub
 /* Launch-level timing of the evolution kernels: when enabled, the context records a
  * pair of HIP events on its stream around every sampled launch, per kernel class.
  * qfdtd_kernel_stats returns, for class `cls` (0 plane, 1 row, 2 column, 3 stencil,
- * 4 measurement), the number of timed launches, their mean duration in ms and the
+ * 4 measurement, 5 slab, 6 pencil), the number of timed launches, their mean duration in ms and the
  * algorithmic bytes one launch of that class moves: every state read once and written once,
  * plus the per-site potential factor, shared by the k states of a solve, read once.
  * While timing is enabled the states of an FFT solve are not split over internal

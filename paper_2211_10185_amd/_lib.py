@@ -44,6 +44,8 @@ F_NO_GRAPH = 4
 F_AB_SCHEME = 8
 F_THREE_GROUPS = 16
 F_STENCIL_1STEP = 32
+F_SPLIT_X2 = 64
+F_SPLIT_NARROW = 128
 
 
 class QfdtdError(RuntimeError):

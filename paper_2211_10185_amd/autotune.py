@@ -4,7 +4,9 @@ For a lattice size N, a state precision and a state count, the solver can run a
 step as
   * the plane schedule (x2-x3 plane pass + x1 column pass: 2 passes per step),
     available where an N^2 plane fits in LDS, or
-  * the row/column schedule (x3 row pass + three column passes: 4 passes),
+  * the row/column schedule (x3 row pass + three column passes: 4 passes), or
+  * the split-x2 schedule (slab pass + pencil pass: 2 passes), for the sizes
+    that have split-x2 kernels, with pencil tiles of 4 or 2 x3 columns,
 and, with k >= 2 states, either carry all states through one stream or split
 them into two (or, with k >= 3, three) groups pipelined on their own streams.  ``tune`` times every candidate
 on the device with the solver's own kernels and records the fastest in a JSON
@@ -22,6 +24,7 @@ from typing import Dict, Iterable, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PLANE_LIMIT = {0: 128, 1: 96}      # largest N whose plane fits LDS (complex64 / complex128)
+SPLIT_SIZES = {0: (256,), 1: ()}   # sizes with split-x2 (slab and pencil) kernels
 _cache: Optional[Dict[str, dict]] = None
 
 
@@ -47,19 +50,20 @@ def key(N: int, precision: int, k: int) -> str:
 def default_schedule(N: int, kinetic: int, precision: int, k: int) -> dict:
     # without a measurement: two streams pay off only once a group's passes fill the GPU
     single = k < 2 or N < 96
-    return {"rowcol": False, "single_stream": single, "groups": 1 if single else 2}
+    return {"rowcol": False, "single_stream": single, "groups": 1 if single else 2, "split": False}
 
 
 def schedule_for(N: int, kinetic: int, precision: int, k: int) -> dict:
     """Tuned schedule if the cache has one for (N, precision, k), else the default."""
     if kinetic == 0:
-        return {"rowcol": False, "single_stream": True, "groups": 1}
+        return {"rowcol": False, "single_stream": True, "groups": 1, "split": False}
     e = _load().get(key(N, precision, k))
     if e is None:
         return default_schedule(N, kinetic, precision, k)
     single = bool(e["single_stream"])
     return {"rowcol": bool(e["rowcol"]), "single_stream": single,
-            "groups": 1 if single else int(e.get("groups", 2))}
+            "groups": 1 if single else int(e.get("groups", 2)), "split": bool(e.get("split", False)),
+            "split_variant": int(e.get("split_variant", 0))}
 
 
 def candidates(N: int, precision: int, k: int):
@@ -68,8 +72,17 @@ def candidates(N: int, precision: int, k: int):
     for rowcol in ([False, True] if plane_ok else [True]):
         groups = [1] if rowcol or k < 2 else ([1, 2, 3] if k >= 3 else [1, 2])
         for g in groups:
-            out.append({"rowcol": rowcol, "single_stream": g == 1, "groups": g})
+            out.append({"rowcol": rowcol, "single_stream": g == 1, "groups": g, "split": False})
+    if N in SPLIT_SIZES[precision]:
+        for v in (0, 1):
+            out.append({"rowcol": False, "single_stream": True, "groups": 1, "split": True, "split_variant": v})
     return out
+
+
+def candidate_name(c: dict) -> str:
+    if c.get("split"):
+        return "split/%dcol" % (4 if c.get("split_variant", 0) == 0 else 2)
+    return ("rowcol" if c["rowcol"] else "plane") + ("/1stream" if c["groups"] == 1 else "/%dstreams" % c["groups"])
 
 
 def time_schedule(N: int, precision: int, k: int, sched: dict, steps: int = 400, kinetic: int = 2,
@@ -81,7 +94,8 @@ def time_schedule(N: int, precision: int, k: int, sched: dict, steps: int = 400,
     from .solver import Solver
     a = 8.0 / N
     s = Solver(N, a, 1.0, kinetic, S.V_HARMONIC, (1.0,), precision=precision, n_states=k,
-               rowcol=sched["rowcol"], groups=sched.get("groups", 1 if sched["single_stream"] else 2))
+               rowcol=sched["rowcol"], groups=sched.get("groups", 1 if sched["single_stream"] else 2),
+               split=sched.get("split", False), split_variant=sched.get("split_variant", 0))
     s.set_states(S.initial_states(N, k, 7))
     dt = a * a / 8
     s.evolve(50, dt)
@@ -112,15 +126,16 @@ def tune(sizes: Iterable[int], precisions: Iterable[int] = (0,), states: Iterabl
     for N in sizes:
         for prec in precisions:
             for k in states:
-                times = {}
+                times, cands = {}, {}
                 for c in candidates(N, prec, k):
-                    name = ("rowcol" if c["rowcol"] else "plane") + ("/1stream" if c["groups"] == 1 else
-                                                                     "/%dstreams" % c["groups"])
+                    name = candidate_name(c)
+                    cands[name] = c
                     times[name] = time_schedule(N, prec, k, c, steps)
                 best = min(times, key=times.get)
-                groups = 1 if best.endswith("1stream") else int(best.split("/")[1][0])
-                entries[key(N, prec, k)] = {"rowcol": best.startswith("rowcol"),
-                                            "single_stream": groups == 1, "groups": groups,
+                c = cands[best]
+                entries[key(N, prec, k)] = {"rowcol": c["rowcol"], "single_stream": c["groups"] == 1,
+                                            "groups": c["groups"], "split": c["split"],
+                                            "split_variant": c.get("split_variant", 0),
                                             "us_per_step": {n: round(v, 2) for n, v in times.items()}}
                 if verbose:
                     print("tune N=%d prec=%d k=%d -> %s %s" % (N, prec, k, best, entries[key(N, prec, k)]["us_per_step"]),

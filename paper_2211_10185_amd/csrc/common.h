@@ -207,6 +207,14 @@ struct FftKernels {
   const void *col[2];
   size_t plane_lds[2], row_lds[2], col_lds[2];
   int plane_nt;
+  // split-x2 two-pass schedule (slab and pencil passes), where instantiated: slab by precision,
+  // pencil (complex64) by tile variant
+  const void *slab[2];
+  size_t slab_lds[2];
+  int slab_nt, split_n1;
+  const void *pencil[2];
+  size_t pencil_lds[2];
+  int pencil_nt[2], pencil_tt[2];
 };
 
 // Multi-size transform-pass kernels of one size group (see fft_inst.hip).

@@ -713,6 +713,341 @@ __global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
   col_body<T, N, LINE_THREADS>(L, e, blk - L.tile_start[e], smem);
 }
 
+// ------------------------------------------------- slab and pencil passes (split x2)
+//
+// For large N the x2 transform is split four-step style, N = N1 N2 with i2 = N2 a + b
+// (a < N1, b < N2):
+//   forward  A (slab pass):   Y[k1][b] = W_N^{b k1} sum_a x[N2 a + b] W_N1^{a k1}, stored at row N2 k1 + b;
+//            B (pencil pass): X[k1 + N1 k2] = sum_b Y[k1][b] W_N2^{b k2},        stored at row N2 k1 + k2;
+//   inverse  B^-1 then A^-1 with conjugate roots, on the same rows.
+// The slab pass holds the N1 rows {N2 a + b} of one x1 plane (b fixed): A^-1, the x3
+// transforms around the potential factor, A.  The pencil pass holds the N2 consecutive rows
+// N2 k1 .. N2 k1 + N2 - 1 of TT consecutive x3 columns over all x1: B, the x1 transforms
+// around the kinetic factor (x2 frequency k1 + N1 k2 at row N2 k1 + k2), B^-1.  One step is
+// then two passes over the state (a pencil pass and a slab pass) instead of a row pass and
+// three column passes.  Between the passes of a chunk the state is held in this split x2
+// order; the chunk's first and last slab passes take it from and return it to real space
+// in natural order.
+
+template <typename T, int N, int N1> __host__ __device__ constexpr size_t slab_lds_t() {
+  return (size_t)(N1 * padded_len(N) + tw_total<T, N>() + N1) * sizeof(C<T>);
+}
+// Pencil tile in LDS: element n (x1) of line l = k2 TT + c at n PC + l.  PC = lines + 4 puts the
+// 16 lanes of one 128-byte LDS pass (4 x1 positions x 4 columns, or 8 x 2) on distinct banks
+// when the B stage writes its outputs.
+template <int N2, int TT> __host__ __device__ constexpr int pencil_pitch() { return N2 * TT + 4; }
+template <typename T, int N, int N2, int TT> __host__ __device__ constexpr size_t pencil_lds_t() {
+  return (size_t)(N * pencil_pitch<N2, TT>() + tw_total<T, N>()) * sizeof(C<T>) + N * sizeof(T);
+}
+
+// Loads and stores of one state with a block-uniform base and a 32-bit per-lane byte offset.
+// The base goes through readfirstlane, so the compiler holds it (plus any uniform offset) in
+// scalar registers and each access needs one 32-bit offset register instead of a 64-bit address:
+// a lane keeps one access per x2 row of a split-x2 stage in flight.
+template <typename T> struct StateBuf {
+  const char *base;
+  __device__ __forceinline__ explicit StateBuf(const void *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    base = (const char *)(((uint64_t)hi << 32) | lo);
+  }
+  __device__ __forceinline__ C<T> load(uint32_t voff, uint32_t soff) const {
+    return *(const C<T> *)(base + soff + voff);
+  }
+  __device__ __forceinline__ void store(C<T> x, uint32_t voff, uint32_t soff) const {
+    *(C<T> *)(const_cast<char *>(base) + soff + voff) = x;
+  }
+};
+
+// Slab pass on tile (plane i1, fast x2 digit b), for each state of the member in turn, so that
+// the potential factor rows of the tile are read from HBM once for all k states.  Steady mode
+// (M_INV | M_MID | M_FWD): A^-1 from HBM, inverse x3, x h^2 (fused with the last inverse and
+// first forward stages), forward x3, A to HBM.  Other modes: chunk start (M_PRE | M_FWD: x h,
+// forward x3, A), chunk end (M_INV | M_POST: A^-1, inverse x3, x h) and plain transforms.
+template <typename T, int N, int N1, int NT>
+__device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, unsigned char *smem) {
+  constexpr int N2 = N / N1;
+  constexpr int P = padded_len(N);
+  constexpr int CQ = (N + NT - 1) / NT;     // x3 columns per thread in the A stages
+  using Rows = RowsGeo<N1, P>;
+  constexpr RPlan PL = plan_of<T, N, false>();
+  constexpr int M = PL.n - 1;
+  static_assert(N % N1 == 0 && PL.n >= 2, "slab pass needs N1 | N and a plan of two or more stages");
+  static_assert(sizeof(T) == 4 && (size_t)N * N * N * 8 < (1ull << 31), "complex64 states below 2 GiB");
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const int i1 = t / N2, b = t - (t / N2) * N2;
+  C<T> *buf = (C<T> *)smem;
+  C<T> *tw = buf + N1 * P;
+  C<T> *wab = tw + tw_total<T, N>();       // W_N^{b k1}, k1 < N1: the twiddles of A
+  load_tw<T, N, NT>(tw, d);
+  for (int k1 = threadIdx.x; k1 < N1; k1 += NT) wab[k1] = ((const C<T> *)d.tw)[(b * k1) % N];
+  constexpr size_t N3 = (size_t)N * N * N;
+  const size_t voff = (size_t)i1 * N * N;
+  const bool vc = d.vcomplex != 0;
+  auto site = [&](int a, int n) -> size_t { return (size_t)(N2 * a + b) * N + n; };
+  auto fac = [&](const void *f, size_t o) -> C<T> {
+    return vc ? ((const C<T> *)f)[voff + o] : mkc<T>(((const T *)f)[voff + o], 0);
+  };
+  // A^-1: the N1 values of each x3 column, conj twiddles, inverse DFT over k1, rows to LDS
+  auto a_inverse_to_lds = [&](const C<T> *g) {
+    const StateBuf<T> sb(g - voff);
+#pragma unroll
+    for (int q = 0; q < CQ; ++q) {
+      const int col = (int)threadIdx.x + q * NT;
+      if (N % NT == 0 || col < N) {
+        C<T> v[N1];
+        const uint32_t vo = (uint32_t)((voff + site(0, col)) * sizeof(C<T>));
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) v[k1] = sb.load(vo, (uint32_t)(k1 * N2 * N * sizeof(C<T>)));
+#pragma unroll
+        for (int k1 = 1; k1 < N1; ++k1) {
+          C<T> w = wab[k1];
+          w.y = -w.y;
+          v[k1] = cmul(v[k1], w);
+        }
+        Dft<N1, true, C<T>>::run(v);
+#pragma unroll
+        for (int a = 0; a < N1; ++a) buf[Rows::at(a, col)] = v[a];
+      }
+    }
+  };
+  // A: columns from LDS rows, DFT over a, twiddles, to HBM at rows N2 k1 + b
+  auto a_forward_from_lds = [&](C<T> *g) {
+    const StateBuf<T> sb(g - voff);
+#pragma unroll
+    for (int q = 0; q < CQ; ++q) {
+      const int col = (int)threadIdx.x + q * NT;
+      if (N % NT == 0 || col < N) {
+        C<T> v[N1];
+#pragma unroll
+        for (int a = 0; a < N1; ++a) v[a] = buf[Rows::at(a, col)];
+        Dft<N1, false, C<T>>::run(v);
+#pragma unroll
+        for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], wab[k1]);
+        const uint32_t vo = (uint32_t)((voff + site(0, col)) * sizeof(C<T>));
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) sb.store(v[k1], vo, (uint32_t)(k1 * N2 * N * sizeof(C<T>)));
+      }
+    }
+  };
+  if (mode == (M_INV | M_MID | M_FWD)) {
+    constexpr int RM = PL.r[M];
+    using SS = SG<Rows, N, RM, NT>;
+    // potential factors of the fused middle stage, held in registers for all k states (one
+    // fetch per tile)
+    C<T> hq[SS::CAPQ][RM];
+#pragma unroll
+    for (int q = 0; q < SS::CAPQ; ++q) {
+      if (SS::active(q)) {
+        int j, bl;
+        SS::jb(q, j, bl);
+#pragma unroll
+        for (int r = 0; r < RM; ++r) hq[q][r] = fac(d.h2fac, site(bl, j + r * SS::NR));
+      }
+    }
+    for (int s = 0; s < d.k; ++s) {
+      C<T> *g = (C<T> *)d.psi + (size_t)s * N3 + voff;
+      __syncthreads();     // the twiddle tables; the previous state's reads of the LDS rows
+      a_inverse_to_lds(g);
+      __syncthreads();
+      lds_stages<T, N, false, true, Rows, NT, 0, M>(buf, tw);
+      {
+        constexpr int NSL = ns_before<T, N, false, M>();
+        C<T> v[SS::CAPQ][RM];
+        st_read<T, N, RM, NSL, true, Rows, NT, tw_off<T, N, false, M>()>(
+            v, tw, [&](int bl, int n) { return buf[Rows::at(bl, n)]; });
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < SS::CAPQ; ++q) {
+          if (SS::active(q)) {
+#pragma unroll
+            for (int r = 0; r < RM; ++r) v[q][r] = vc ? cmul(v[q][r], hq[q][r]) : cscale(v[q][r], hq[q][r].x);
+            Dft<RM, false, C<T>>::run(v[q]);
+          }
+        }
+        st_write<T, N, RM, 1, Rows, NT>(v, [&](int bl, int n, C<T> x) { buf[Rows::at(bl, n)] = x; });
+        __syncthreads();
+      }
+      lds_stages<T, N, true, false, Rows, NT, 1, PL.n>(buf, tw);
+      a_forward_from_lds(g);
+    }
+    return;
+  }
+#ifndef QF_PROBE_NO_GENERIC
+  for (int s = 0; s < d.k; ++s) {
+    C<T> *g = (C<T> *)d.psi + (size_t)s * N3 + voff;
+    __syncthreads();       // the twiddle tables; the previous state's reads of the LDS rows
+    if (mode & M_INV) {
+      a_inverse_to_lds(g);
+    } else {
+      for (int idx = threadIdx.x; idx < N1 * N; idx += NT) {
+        const int a = idx / N, n = idx - a * N;
+        C<T> v = g[site(a, n)];
+        if (mode & M_PRE) {
+          const C<T> h = fac(d.hfac, site(a, n));
+          v = vc ? cmul(v, h) : cscale(v, h.x);
+        }
+        buf[Rows::at(a, n)] = v;
+      }
+    }
+    __syncthreads();
+    if (mode & M_INV) fft_lines_t<T, N, true, Rows, NT>(buf, tw);
+    if (mode & (M_MID | M_POST)) {
+      for (int idx = threadIdx.x; idx < N1 * N; idx += NT) {
+        const int a = idx / N, n = idx - a * N;
+        const C<T> h = fac((mode & M_MID) ? d.h2fac : d.hfac, site(a, n));
+        const int o = Rows::at(a, n);
+        buf[o] = vc ? cmul(buf[o], h) : cscale(buf[o], h.x);
+      }
+      __syncthreads();
+    }
+    if (mode & M_FWD) {
+      fft_lines_t<T, N, false, Rows, NT>(buf, tw);
+      a_forward_from_lds(g);
+    } else {
+      for (int idx = threadIdx.x; idx < N1 * N; idx += NT) {
+        const int a = idx / N, n = idx - a * N;
+        g[site(a, n)] = buf[Rows::at(a, n)];
+      }
+    }
+  }
+#endif
+}
+
+// Pencil pass on tile (state s, slow x2 frequency k1, x3 columns c0 .. c0 + TT - 1), steady
+// mode only (B, forward x1, x e^{-dt T(k)}/N^3, inverse x1, B^-1): the chunk's slab passes
+// bracket every pencil pass.
+template <typename T, int N, int N2, int TT, int NT>
+__device__ __forceinline__ void pencil_body(const LaunchList &L, int e, int t, unsigned char *smem) {
+  constexpr int N1 = N / N2;
+  constexpr int NL = N2 * TT;
+  constexpr int PC = pencil_pitch<N2, TT>();
+  constexpr int NCB = N / TT;
+  constexpr int PPT = (N * TT + NT - 1) / NT;    // (x1, column) positions per thread in the B stages
+  using Geo = TileGeo<NL, PC>;
+  constexpr RPlan PL = plan_of<T, N, false>();
+  constexpr int M = PL.n - 1;
+  static_assert(N % N2 == 0 && N % TT == 0 && PL.n >= 2, "pencil tile must divide the lattice");
+  static_assert(sizeof(T) == 4 && (size_t)N * N * N * 8 < (1ull << 31), "complex64 states below 2 GiB");
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const int cb = t % NCB;
+  const int u = t / NCB;
+  const int k1 = u % N1, s = u / N1;
+  const int c0 = cb * TT;
+  C<T> *buf = (C<T> *)smem;
+  C<T> *tw = buf + N * PC;
+  T *ktl = (T *)(tw + tw_total<T, N>());      // the per-axis kinetic table
+  load_tw<T, N, NT>(tw, d);
+  for (int i = threadIdx.x; i < N; i += NT) ktl[i] = ((const T *)d.ktab)[i];
+  constexpr size_t N3 = (size_t)N * N * N;
+  const StateBuf<T> sb((C<T> *)d.psi + (size_t)s * N3);
+  // the k-space factor of kin_factor_t, with the table read from LDS
+  const bool rel = d.kin == KIN_REL, ab = d.scheme == SCHEME_AB;
+  const T mm = (T)d.m, dtT = (T)d.dt, in3 = (T)d.inv_n3, dtn = (T)(d.dt * d.inv_n3);
+  auto kfac = [&](int i1, int i2, int i3) -> T {
+    if (rel) {
+      const T p2 = ktl[i1] + ktl[i2] + ktl[i3];
+      const float tk = p2 * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(p2 + mm * mm) + mm);
+      if (ab) return tk * dtn;
+      return __builtin_amdgcn_exp2f(-dtT * 1.4426950408889634f * tk) * in3;
+    }
+    if (ab) return (ktl[i1] + ktl[i2] + ktl[i3]) * dtn;
+    return ktl[i1] * ktl[i2] * ktl[i3] * in3;
+  };
+  // byte offset of (x1 plane i1, row N2 k1, column c0 + c); rows b apart by b N elements
+  auto at = [&](int i1, int c) -> uint32_t {
+    return (uint32_t)(((size_t)i1 * N * N + (size_t)(N2 * k1) * N + c0 + c) * sizeof(C<T>));
+  };
+  __syncthreads();       // the twiddle tables
+  // B: DFT over the N2 rows of each (x1, column) position, outputs to the x1 lines (k2, c)
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int pos = (int)threadIdx.x + q * NT;
+    if ((N * TT) % NT == 0 || pos < N * TT) {
+      const int i1 = pos / TT, c = pos - (pos / TT) * TT;
+      C<T> v[N2];
+#pragma unroll
+      for (int bb = 0; bb < N2; ++bb) v[bb] = sb.load(at(i1, c), (uint32_t)(bb * N * sizeof(C<T>)));
+      Dft<N2, false, C<T>>::run(v);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) buf[Geo::at(k2 * TT + c, i1)] = v[k2];
+    }
+  }
+  __syncthreads();
+  lds_stages<T, N, false, false, Geo, NT, 0, M>(buf, tw);
+  {
+    constexpr int R = PL.r[M];
+    constexpr int NSL = ns_before<T, N, false, M>();
+    using SS = SG<Geo, N, R, NT>;
+    C<T> v[SS::CAPQ][R];
+    st_read<T, N, R, NSL, false, Geo, NT, tw_off<T, N, false, M>()>(v, tw, [&](int l, int n) { return buf[Geo::at(l, n)]; });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SS::CAPQ; ++q) {
+      if (SS::active(q)) {
+        int j, l;
+        SS::jb(q, j, l);
+        const int k2 = l / TT, c = l - (l / TT) * TT;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = cscale(v[q][r], kfac(j + r * SS::NR, k1 + N1 * k2, c0 + c));
+        Dft<R, true, C<T>>::run(v[q]);
+      }
+    }
+    st_write<T, N, R, 1, Geo, NT>(v, [&](int l, int n, C<T> x) { buf[Geo::at(l, n)] = x; });
+    __syncthreads();
+  }
+  lds_stages<T, N, true, true, Geo, NT, 1, PL.n>(buf, tw);
+  // B^-1: inverse DFT over k2 of each position, to the N2 rows in HBM
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int pos = (int)threadIdx.x + q * NT;
+    if ((N * TT) % NT == 0 || pos < N * TT) {
+      const int i1 = pos / TT, c = pos - (pos / TT) * TT;
+      C<T> v[N2];
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) v[k2] = buf[Geo::at(k2 * TT + c, i1)];
+      Dft<N2, true, C<T>>::run(v);
+#pragma unroll
+      for (int bb = 0; bb < N2; ++bb) sb.store(v[bb], at(i1, c), (uint32_t)(bb * N * sizeof(C<T>)));
+    }
+  }
+}
+
+// Split-x2 tile shapes per size (complex64): N1 x N2, the slab block, and the pencil variants:
+// TT x3 columns per pencil tile with PENCIL_NT threads (one (x1, column) position per thread).
+// Variant 0 holds 4 columns (144 KiB of LDS at N = 256, one tile per CU, 32-byte row pieces),
+// variant 1 holds 2 columns (77 KiB, two tiles per CU, 16-byte row pieces).
+template <int N> struct SplitShape { static constexpr bool ok = false; };
+template <> struct SplitShape<256> {
+  static constexpr bool ok = true;
+  static constexpr int N1 = 16, N2 = 16, SLAB_NT = 256;
+  static constexpr int TT[2] = {4, 2};
+};
+template <int N, int V> __host__ __device__ constexpr int pencil_nt() { return N * SplitShape<N>::TT[V]; }
+
+// Pencil block order: runs of consecutive x3 tiles per XCD, so that the TT-column pieces of one
+// 128-byte row segment are fetched by blocks that share an L2.
+constexpr int PENCIL_XCD_RUN = 16;
+
+template <typename T, int N>
+__global__ void __launch_bounds__(SplitShape<N>::SLAB_NT) k_slab_t(const LaunchList L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using SH = SplitShape<N>;
+  const int e = find_entry(L, blockIdx.x);
+  slab_body<T, N, SH::N1, SH::SLAB_NT>(L, e, blockIdx.x - L.tile_start[e], smem);
+}
+
+template <typename T, int N, int V>
+__global__ void __launch_bounds__((pencil_nt<N, V>())) k_pencil_t(const LaunchList L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using SH = SplitShape<N>;
+  const int blk = xcd_block_chunked(blockIdx.x, gridDim.x, PENCIL_XCD_RUN);
+  const int e = find_entry(L, blk);
+  pencil_body<T, N, SH::N2, SH::TT[V], pencil_nt<N, V>()>(L, e, blk - L.tile_start[e], smem);
+}
+
 // ------------------------------------------------------------ dispatch table
 
 
@@ -737,6 +1072,21 @@ template <int N> void register_size(FftKernels *tab) {
   k.col[1] = (const void *)k_col_t<double, N>;
   k.col_lds[0] = col_lds_t<float, N>();
   k.col_lds[1] = col_lds_t<double, N>();
+  if constexpr (SplitShape<N>::ok) {
+    using SH = SplitShape<N>;
+    k.slab[0] = (const void *)k_slab_t<float, N>;
+    k.slab_lds[0] = slab_lds_t<float, N, SH::N1>();
+    k.slab_nt = SH::SLAB_NT;
+    k.split_n1 = SH::N1;
+    k.pencil[0] = (const void *)k_pencil_t<float, N, 0>;
+    k.pencil[1] = (const void *)k_pencil_t<float, N, 1>;
+    k.pencil_lds[0] = pencil_lds_t<float, N, SH::N2, SH::TT[0]>();
+    k.pencil_lds[1] = pencil_lds_t<float, N, SH::N2, SH::TT[1]>();
+    k.pencil_nt[0] = pencil_nt<N, 0>();
+    k.pencil_nt[1] = pencil_nt<N, 1>();
+    k.pencil_tt[0] = SH::TT[0];
+    k.pencil_tt[1] = SH::TT[1];
+  }
 }
 
 }  // namespace qf

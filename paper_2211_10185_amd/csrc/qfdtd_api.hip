@@ -61,17 +61,17 @@ extern thread_local std::string g_create_error;
 
 namespace {
 
-enum { TC_PLANE = 0, TC_ROW = 1, TC_COL = 2, TC_STENCIL = 3, TC_MEAS = 4, TC_N = 5 };
+enum { TC_PLANE = 0, TC_ROW = 1, TC_COL = 2, TC_STENCIL = 3, TC_MEAS = 4, TC_SLAB = 5, TC_PENCIL = 6, TC_N = 7 };
 
 struct Timer {
   int every = 0;
-  long long seen[TC_N] = {0, 0, 0, 0, 0};
+  long long seen[TC_N] = {0, 0, 0, 0, 0, 0, 0};
   struct Rec { hipEvent_t a, b; int cls; double bytes; };
   std::vector<Rec> pool;
   size_t used = 0;
-  long long count[TC_N] = {0, 0, 0, 0, 0};
-  double sum_ms[TC_N] = {0, 0, 0, 0, 0};
-  double sum_bytes[TC_N] = {0, 0, 0, 0, 0};
+  long long count[TC_N] = {0, 0, 0, 0, 0, 0, 0};
+  double sum_ms[TC_N] = {0, 0, 0, 0, 0, 0, 0};
+  double sum_bytes[TC_N] = {0, 0, 0, 0, 0, 0, 0};
 };
 
 bool smooth235(int n) {
@@ -128,9 +128,11 @@ hipError_t fft_table_init() {
     }
   for (int n = 0; n <= 256; ++n)
     for (int w = 0; w < 2; ++w) {
-      const void *fs[3] = {g_fft[n].plane[w], g_fft[n].row[w], g_fft[n].col[w]};
-      const size_t ls[3] = {g_fft[n].plane_lds[w], g_fft[n].row_lds[w], g_fft[n].col_lds[w]};
-      for (int q = 0; q < 3; ++q)
+      // (pencil entries are tile variants of complex64, not precisions)
+      const void *fs[5] = {g_fft[n].plane[w], g_fft[n].row[w], g_fft[n].col[w], g_fft[n].slab[w], g_fft[n].pencil[w]};
+      const size_t ls[5] = {g_fft[n].plane_lds[w], g_fft[n].row_lds[w], g_fft[n].col_lds[w], g_fft[n].slab_lds[w],
+                            g_fft[n].pencil_lds[w]};
+      for (int q = 0; q < 5; ++q)
         if (fs[q]) {
           hipError_t e = hipFuncSetAttribute(fs[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ls[q]);
           if (e != hipSuccess) return e;
@@ -178,6 +180,10 @@ int col_tiles(int N, int k, bool dbl) {
   const int tc = col_tile(dbl);
   return k * N * ((N + tc - 1) / tc);
 }
+// split-x2 schedule: slab tiles (x1 plane, fast x2 digit; a tile carries every state), pencil
+// tiles (state, slow x2 frequency, x3 column block)
+int slab_tiles(int N) { return N * (N / g_fft[N].split_n1); }
+int pencil_tiles(int N, int k, int v) { return k * g_fft[N].split_n1 * (N / g_fft[N].pencil_tt[v]); }
 
 }  // namespace
 
@@ -188,6 +194,8 @@ struct qfdtd_ctx {
   double a = 0, m = 0;
   int sectors[MAX_STATES] = {0};
   bool any_parity = false, vcomplex = false, dbl = false, plane = false, plane64 = false;
+  bool split = false;           // FFT kinds: the two-pass split-x2 schedule (slab and pencil passes)
+  int pencil_v = 0;             // split-x2: pencil tile variant (0: 4 x3 columns, 1: 2)
   int scheme = SCHEME_SPLIT;    // FFT kinds: split-operator step or A/B update
   hipStream_t st = nullptr;
   qfdtd_alloc_fn af = nullptr;
@@ -314,7 +322,8 @@ struct Entry {
   int aux;
 };
 
-enum Fam { F_PLANE, F_ROW, F_COL, F_STENCIL, F_STENCIL2, F_PARITY, F_TO64, F_GRAM, F_APPLY, F_EPART, F_KPART, F_GFIN, F_EFIN };
+enum Fam { F_PLANE, F_ROW, F_COL, F_STENCIL, F_STENCIL2, F_PARITY, F_TO64, F_GRAM, F_APPLY, F_EPART, F_KPART, F_GFIN, F_EFIN,
+           F_SLAB, F_PENCIL };
 
 // Algorithmic bytes moved by one member's share of a launch (for timing): every state is read
 // and written once, and the per-site potential factor, which all k states of the member share,
@@ -330,10 +339,12 @@ double entry_bytes(const Entry &e, Fam f) {
   switch (f) {
     case F_PLANE:
     case F_ROW:
+    case F_SLAB:
       // A/B combine: read alt and psi and V, write psi (and alt when the forward follows)
       if (e.mode & M_COMB) return n * (3 * s + ((e.mode & M_FWD) ? s : 0.0)) + n3 * fsz;
       return n * 2 * s + ((e.mode & (M_PRE | M_MID | M_POST)) ? n3 * fsz : 0.0);
-    case F_COL: return n * 2 * s;
+    case F_COL:
+    case F_PENCIL: return n * 2 * s;
     case F_STENCIL: return n * 2 * s + n3 * fsz;
     case F_STENCIL2: return 2 * (n * 2 * s + n3 * fsz);    // two steps per launch
     default: return n * 2 * s;
@@ -400,6 +411,8 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
       if (f == F_PLANE) l = K.plane_lds[dbl];
       else if (f == F_ROW) l = K.row_lds[dbl];
       else if (f == F_COL) l = K.col_lds[dbl];
+      else if (f == F_SLAB) l = K.slab_lds[dbl];
+      else if (f == F_PENCIL) l = K.pencil_lds[e.c->pencil_v];
       if (l > lds) lds = l;
       if (grp >= 0 && (f == F_PLANE || f == F_ROW || f == F_COL))
         lds = g_grp_lds[grp][f == F_PLANE ? 0 : (f == F_ROW ? 1 : 2)][dbl];
@@ -415,6 +428,8 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
     else if (f == F_ROW) cls = TC_ROW;
     else if (f == F_COL) cls = TC_COL;
     else if (f == F_STENCIL || f == F_STENCIL2) cls = TC_STENCIL;
+    else if (f == F_SLAB) cls = TC_SLAB;
+    else if (f == F_PENCIL) cls = TC_PENCIL;
     const int tix = cls >= 0 ? tbegin(c0, cls, bytes, st) : -1;
     const FftKernels &K = g_fft[es[base].c->N];
     void *kargs[] = {(void *)&L};
@@ -434,6 +449,8 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
       case F_PLANE: go(fplane, ntplane, lds); break;
       case F_ROW: go(frow, LINE_THREADS, lds); break;
       case F_COL: go(fcol, LINE_THREADS, lds); break;
+      case F_SLAB: go(K.slab[dbl], K.slab_nt, lds); break;
+      case F_PENCIL: go(K.pencil[c0->pencil_v], K.pencil_nt[c0->pencil_v], lds); break;
       case F_STENCIL: go(stencil_kernel(dbl), RED_THREADS, 0); break;
       case F_STENCIL2: go(stencil2_kernel(), S2_THREADS, 0); break;
       case F_PARITY: launch_parity(L, total, dbl, st); break;
@@ -458,6 +475,21 @@ qfdtd_status run_by_k(Fam f, std::vector<Entry> &es, bool dbl) {
     for (auto &e : es)
       if (e.c->k == KS) sub.push_back(e);
     QF_TRY(run_family(f, sub, dbl, KS));
+  }
+  return QFDTD_OK;
+}
+
+// run a single-size kernel family once per distinct N and pencil variant (split-x2 passes)
+qfdtd_status run_by_size(Fam f, std::vector<Entry> &es, bool dbl) {
+  std::vector<int> keys;
+  auto key_of = [&](const Entry &e) { return e.c->N * 4 + (f == F_PENCIL ? e.c->pencil_v : 0); };
+  for (auto &e : es)
+    if (std::find(keys.begin(), keys.end(), key_of(e)) == keys.end()) keys.push_back(key_of(e));
+  for (int kk : keys) {
+    std::vector<Entry> one;
+    for (auto &e : es)
+      if (key_of(e) == kk) one.push_back(e);
+    QF_TRY(run_family(f, one, dbl, -1));
   }
   return QFDTD_OK;
 }
@@ -569,11 +601,15 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
   const bool dbl = ms[0]->dbl;
   int maxn = 0;
   for (int v : n) maxn = v > maxn ? v : maxn;
-  std::vector<Entry> pl, rw, c2, c1, sten, sten2;
+  std::vector<Entry> pl, rw, c2, c1, sten, sten2, sl, pen;
   // chunk start: h then forward transforms along x3 (and x2)
   for (size_t j = 0; j < ms.size(); ++j) {
     qfdtd_ctx *c = ms[j];
     if (!c->fft() || n[j] <= 0) continue;
+    if (c->split) {
+      sl.push_back({c, 0, M_PRE | M_FWD, slab_tiles(c->N), 0});
+      continue;
+    }
     // A/B update: the forward transform of psi goes to alt; psi stays for the combine
     const uint32_t start = c->scheme == SCHEME_AB ? (uint32_t)(M_FWD | M_ALT) : (uint32_t)(M_PRE | M_FWD);
     const uint32_t onalt = c->scheme == SCHEME_AB ? (uint32_t)M_ALT : 0u;
@@ -583,11 +619,12 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
       c2.push_back({c, 0, M_FWD | onalt, col_tiles(c->N, c->k, dbl), 0});
     }
   }
+  QF_TRY(run_by_size(F_SLAB, sl, dbl));
   QF_TRY(run_family(F_PLANE, pl, dbl));
   QF_TRY(run_family(F_ROW, rw, dbl));
   QF_TRY(run_family(F_COL, c2, dbl));
   for (int s = 0; s < maxn; ++s) {
-    c1.clear(); c2.clear(); pl.clear(); rw.clear(); sten.clear(); sten2.clear();
+    c1.clear(); c2.clear(); pl.clear(); rw.clear(); sten.clear(); sten2.clear(); sl.clear(); pen.clear();
     std::vector<Entry> c2f;
     for (size_t j = 0; j < ms.size(); ++j) {
       qfdtd_ctx *c = ms[j];
@@ -603,6 +640,12 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
         continue;
       }
       const bool last = (s == n[j] - 1);
+      if (c->split) {
+        pen.push_back({c, 0, M_FWD | M_KIN | M_INV, pencil_tiles(c->N, c->k, c->pencil_v), 0});
+        sl.push_back({c, 0, last ? (uint32_t)(M_INV | M_POST) : (uint32_t)(M_INV | M_MID | M_FWD),
+                      slab_tiles(c->N), 0});
+        continue;
+      }
       const bool ab = c->scheme == SCHEME_AB;
       const uint32_t onalt = ab ? (uint32_t)M_ALT : 0u;
       uint32_t rs = last ? (M_INV | M_POST) : (M_INV | M_MID | M_FWD);
@@ -617,6 +660,8 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
     }
     QF_TRY(run_family(F_COL, c1, dbl));
     QF_TRY(run_family(F_COL, c2, dbl));
+    QF_TRY(run_by_size(F_PENCIL, pen, dbl));
+    QF_TRY(run_by_size(F_SLAB, sl, dbl));
     QF_TRY(run_family(F_PLANE, pl, dbl));
     QF_TRY(run_family(F_ROW, rw, dbl));
     QF_TRY(run_family(F_COL, c2f, dbl));
@@ -918,7 +963,10 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     return fail(nullptr, QFDTD_E_UNSUPPORTED_N, "no transform kernels for this N");
   }
   c->scheme = (c->fft() && (o.flags & QFDTD_F_AB_SCHEME)) ? SCHEME_AB : SCHEME_SPLIT;
-  c->plane = c->fft() && g_fft[N].plane[c->dbl ? 1 : 0] != nullptr && !(o.flags & QFDTD_F_ROWCOL);
+  c->split = c->fft() && c->scheme == SCHEME_SPLIT && (o.flags & QFDTD_F_SPLIT_X2) &&
+             g_fft[N].slab[c->dbl ? 1 : 0] != nullptr;
+  c->pencil_v = (o.flags & QFDTD_F_SPLIT_NARROW) ? 1 : 0;
+  c->plane = c->fft() && g_fft[N].plane[c->dbl ? 1 : 0] != nullptr && !(o.flags & QFDTD_F_ROWCOL) && !c->split;
   c->plane64 = c->fft() && g_fft[N].plane[1] != nullptr;
   c->nblk_red = (int)((n3 + 2047) / 2048);
   if (c->nblk_red > 1024) c->nblk_red = 1024;

@@ -80,7 +80,8 @@ class Solver:
                  measure_every: int = 50, trace: bool = False, torch_alloc: bool = True,
                  single_stream: Optional[bool] = None, rowcol: Optional[bool] = None,
                  graphs: bool = True, scheme: int = 0, groups: Optional[int] = None,
-                 fused_stencil: bool = True):
+                 fused_stencil: bool = True, split: Optional[bool] = None,
+                 split_variant: Optional[int] = None):
         torch = _torch()
         self.N, self.a, self.m, self.kinetic = int(N), float(a), float(m), int(kinetic)
         self.precision, self.k = int(precision), int(n_states)
@@ -99,20 +100,27 @@ class Solver:
         # state groups on their own streams (FFT plane schedule): 1, 2 or 3
         if groups is not None:
             single_stream = int(groups) <= 1
-        if single_stream is None or rowcol is None or groups is None:
+        if single_stream is None or rowcol is None or groups is None or split is None:
             from .autotune import schedule_for
             tuned = schedule_for(self.N, self.kinetic, self.precision, self.k)
             single_stream = tuned["single_stream"] if single_stream is None else single_stream
             rowcol = tuned["rowcol"] if rowcol is None else rowcol
+            if split is None:
+                split = tuned.get("split", False)
+                if split_variant is None:
+                    split_variant = int(tuned.get("split_variant", 0))
             if groups is None:
                 groups = 1 if single_stream else int(tuned.get("groups", 2))
-        self.schedule = {"single_stream": bool(single_stream), "rowcol": bool(rowcol), "groups": int(groups)}
+        split_variant = int(split_variant or 0)
+        self.schedule = {"single_stream": bool(single_stream), "rowcol": bool(rowcol), "groups": int(groups),
+                         "split": bool(split), "split_variant": split_variant}
         # scheme 1: the A/B update (psi' = A psi - B dt H_K psi) for the FFT kinetic terms
         self.scheme = int(scheme)
         opt.flags = ((L.F_SINGLE_STREAM if single_stream else 0) | (L.F_ROWCOL if rowcol else 0)
                      | (0 if graphs else L.F_NO_GRAPH) | (L.F_AB_SCHEME if self.scheme == 1 else 0)
                      | (L.F_THREE_GROUPS if int(groups) == 3 else 0)
-                     | (0 if fused_stencil else L.F_STENCIL_1STEP))
+                     | (0 if fused_stencil else L.F_STENCIL_1STEP) | (L.F_SPLIT_X2 if split else 0)
+                     | (L.F_SPLIT_NARROW if split and split_variant == 1 else 0))
         opt.hip_stream = ct.c_void_p(self.stream.cuda_stream)
         if self._alloc is not None:
             opt.dev_alloc = self._alloc.alloc
