@@ -54,3 +54,34 @@ def wavefunction_errors(psi, psi_ref, E_ref, tol_deg=1e-6):
             d = subspace_distance(psi[g], psi_ref[g])
             errs[g] = d
     return errs
+
+
+def sampled_state_errors(psi_sites, ref_sites, q, E_ref, tol_deg=1e-6):
+    """L2 errors of whole-lattice states estimated from their values at sampled sites.
+
+    ``psi_sites``, ``ref_sites``: [k, n] values of the (normalised) states at n sites drawn
+    with replacement from the density q ([n], q(x_j) at the sampled sites), so that
+    sum_x |f(x)|^2 ~ mean_j |f(x_j)|^2 / q(x_j).  Each state is aligned by the phase that
+    minimises the sampled residual; a (near-)degenerate cluster by the unitary that does
+    (weighted orthogonal Procrustes), which makes the result the cluster's subspace distance.
+    Returns the relative residual per state."""
+    psi_sites = np.asarray(psi_sites)
+    ref_sites = np.asarray(ref_sites)
+    w = 1.0 / (len(q) * np.asarray(q))
+    errs = np.zeros(ref_sites.shape[0])
+    for g in degenerate_clusters(E_ref, tol_deg):
+        A = ref_sites[g]              # [m, n]
+        B = psi_sites[g]
+        M = (A * w) @ B.conj().T      # sum_j w_j A_j B_j^H, [m, m]
+        U, _, Vh = np.linalg.svd(M)
+        R = U @ Vh                    # the unitary closest to mapping B onto A
+        D = R @ B - A
+        for a, i in enumerate(g):
+            errs[i] = np.sqrt(np.sum(w * np.abs(D[a]) ** 2) / np.sum(w * np.abs(A[a]) ** 2))
+    return errs
+
+
+def energy_rel_errors(E, E_ref, floor=1e-12):
+    """Plain |E - E_ref| / |E_ref| per level (printed beside the spread-normalised metric)."""
+    E_ref = np.asarray(E_ref)
+    return np.abs(np.asarray(E) - E_ref) / np.maximum(np.abs(E_ref), floor)
