@@ -212,6 +212,24 @@ qfdtd_status qfdtd_batch_evolve(qfdtd_ctx *const *members, int32_t n, const int6
  * caller-owned.  Synchronises the stream.  QFDTD_E_STATE if a state is unset. */
 qfdtd_status qfdtd_gram_matrix(qfdtd_ctx *c, double *G);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the FP64 Gram matrix of qfdtd_gram_matrix, of k
+ * states given by a device pointer, with no context and no allocation.  Its partial sums live
+ * in a fixed device array inside the library (576 KiB on each GPU that runs it, held until the
+ * process ends); every call on a GPU uses that GPU's array, so calls that overlap in time on
+ * one GPU (two streams, two host threads) race and must be serialised by the caller.
+ *   psi:       device, [k][n_sites] interleaved complex64 (precision 0) or complex128 (1),
+ *              caller-owned, read only.
+ *   n_sites:   1 .. QFDTD_NOALLOC_MAX_SITES; k: 1..8.
+ *   G:         device, [k][k][2] FP64 (re, im), row-major, caller-owned; written on the stream.
+ *   hip_stream: hipStream_t (NULL = null stream).  Stream-ordered; nothing is synchronised.
+ * Same summation order as qfdtd_gram_matrix for the same states, so the same bits.
+ * QFDTD_E_INVALID for a NULL pointer or a size beyond these limits (message in
+ * qfdtd_last_error(NULL)); QFDTD_E_DEVICE if the launch fails. */
+#define QFDTD_NOALLOC_MAX_SITES (1ll << 27)
+qfdtd_status qfdtd_gram_matrix_noalloc(const void *psi, int64_t n_sites, int32_t k, int32_t precision,
+                                       double *G, void *hip_stream);
+
 /* Batched energy readout: energies[2*(j*kmax + i) + {0,1}] for member j, state i < k_j.
  * kmax = largest k among the members.  Synchronises the (common) stream. */
 qfdtd_status qfdtd_batch_energies(qfdtd_ctx *const *members, int32_t n, double *energies);

@@ -79,6 +79,7 @@ _sig = {
     "qfdtd_batch_evolve": (ct.c_int, [ct.POINTER(P), ct.c_int32, ct.POINTER(ct.c_int64), DP]),
     "qfdtd_batch_energies": (ct.c_int, [ct.POINTER(P), ct.c_int32, DP]),
     "qfdtd_gram_matrix": (ct.c_int, [P, DP]),
+    "qfdtd_gram_matrix_noalloc": (ct.c_int, [P, ct.c_int64, ct.c_int32, ct.c_int32, P, P]),
     "qfdtd_read_potential_ascii": (ct.c_int, [ct.c_char_p, ct.c_int32, DP]),
     "qfdtd_write_potential_ascii": (ct.c_int, [ct.c_char_p, ct.c_int32, DP]),
     "qfdtd_footprint": (ct.c_size_t, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32]),

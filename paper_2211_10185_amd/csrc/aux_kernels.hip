@@ -526,17 +526,12 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double *ou
   }
 }
 
-// Gram partials G_ij = sum conj(psi_i) psi_j, i <= j, over one block's range of sites.
+// Gram partials G_ij = sum conj(psi_i) psi_j, i <= j, over block blk's range of the N3 sites
+// (nblk blocks), written to out[0 .. 2 NP).
 template <typename T, int KS>
-__global__ void __launch_bounds__(RED_THREADS) k_gram(const LaunchList L) {
+__device__ __forceinline__ void gram_partials(const C<T> *src, size_t N3, int nblk, int blk, double *out) {
   constexpr int NP = KS * (KS + 1) / 2;
-  const int e = find_entry(L, blockIdx.x);
-  const PassDesc &d = *(const PassDesc *)L.descp[e];
-  const uint32_t mode = L.mode[e];
-  const int blk = blockIdx.x - L.tile_start[e];
-  const size_t N3 = (size_t)d.N * d.N * d.N;
-  const C<T> *src = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi);
-  const size_t chunk = (N3 + d.nblk_red - 1) / d.nblk_red;
+  const size_t chunk = (N3 + nblk - 1) / nblk;
   const size_t lo = blk * chunk, hi = (lo + chunk < N3) ? lo + chunk : N3;
   double acc[2 * NP];
 #pragma unroll
@@ -557,7 +552,24 @@ __global__ void __launch_bounds__(RED_THREADS) k_gram(const LaunchList L) {
         acc[2 * p + 1] += v[i].x * v[j].y - v[i].y * v[j].x;
       }
   }
-  block_reduce_store<2 * NP>(acc, d.partials + (size_t)blk * (2 * MAX_PAIRS));
+  block_reduce_store<2 * NP>(acc, out);
+}
+
+template <typename T, int KS>
+__global__ void __launch_bounds__(RED_THREADS) k_gram(const LaunchList L) {
+  const int e = find_entry(L, blockIdx.x);
+  const PassDesc &d = *(const PassDesc *)L.descp[e];
+  const uint32_t mode = L.mode[e];
+  const int blk = blockIdx.x - L.tile_start[e];
+  const size_t N3 = (size_t)d.N * d.N * d.N;
+  const C<T> *src = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi);
+  gram_partials<T, KS>(src, N3, d.nblk_red, blk, d.partials + (size_t)blk * (2 * MAX_PAIRS));
+}
+
+// The same partials for k states given by a plain pointer ([k][n] interleaved complex).
+template <typename T, int KS>
+__global__ void __launch_bounds__(RED_THREADS) k_gram_flat(const C<T> *psi, size_t n, int nblk, double *partials) {
+  gram_partials<T, KS>(psi, n, nblk, blockIdx.x, partials + (size_t)blockIdx.x * (2 * MAX_PAIRS));
 }
 
 __device__ __forceinline__ int pair_index(int i, int j, int KS) { return i * KS - i * (i - 1) / 2 + (j - i); }
@@ -599,6 +611,22 @@ __device__ void block_sum_columns(const double *part, int nb, int q0, int nq, do
 __global__ void __launch_bounds__(RED_THREADS) k_gram_sum(const double *partials, int nb, int nq, double *out) {
   for (int q0 = 0; q0 < nq; q0 += SUMQ)
     block_sum_columns(partials, nb, q0, nq - q0 < SUMQ ? nq - q0 : SUMQ, out + q0);
+}
+
+// The k x k Gram matrix from nb rows of partials: the pair sums in the fixed order of
+// k_gram_sum, then the Hermitian matrix G[i][j] = (re, im), row-major, as qfdtd_gram_matrix
+// returns it.
+__global__ void __launch_bounds__(RED_THREADS) k_gram_full(const double *partials, int nb, int KS, double *G) {
+  __shared__ double Gs[MAX_PAIRS * 2];
+  const int NP = KS * (KS + 1) / 2;
+  for (int q0 = 0; q0 < 2 * NP; q0 += SUMQ)
+    block_sum_columns(partials, nb, q0, 2 * NP - q0 < SUMQ ? 2 * NP - q0 : SUMQ, Gs + q0);
+  for (int t = threadIdx.x; t < KS * KS; t += blockDim.x) {
+    const int i = t / KS, j = t - (t / KS) * KS;
+    const int p = i <= j ? pair_index(i, j, KS) : pair_index(j, i, KS);
+    G[2 * t] = Gs[2 * p];
+    G[2 * t + 1] = i <= j ? Gs[2 * p + 1] : -Gs[2 * p + 1];
+  }
 }
 
 // Sum the partials (fixed order), Cholesky G = R^H R per sector, coef = R^{-1}.
@@ -948,4 +976,87 @@ void launch_energy_finalize(const LaunchList &L, hipStream_t st) {
   hipLaunchKernelGGL(k_energy_finalize, dim3(L.n), dim3(RED_THREADS), 0, st, L);
 }
 
+// ------------------------------------------------ Gram matrix without allocation
+
+// Device memory of qfdtd_gram_matrix_noalloc: the FP64 partial sums of one Gram sweep.  A
+// file-scope array, so that the entry point allocates nothing; every call on a GPU uses that
+// GPU's copy.  In host code `scratch` names a host-side stand-in, not device memory: its
+// device address comes from hipGetSymbolAddress, once per device (gram_scratch_ptr).
+static __device__ __align__(256) double scratch[MAX_RED_BLOCKS * 2 * MAX_PAIRS];
+
 }  // namespace qf
+
+#include <mutex>
+#include <string>
+#include "qfdtd.h"
+
+extern thread_local std::string g_create_error;
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[MAX_DEVICES] = {nullptr};
+
+// Device address of `scratch` on the current device, looked up on the first call there.
+qfdtd_status gram_scratch_ptr(double **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+    g_create_error = std::string("qfdtd_gram_matrix_noalloc: no current device: ") + hipGetErrorString(e);
+    return QFDTD_E_DEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(qf::scratch));
+    if (e != hipSuccess || !p) {
+      g_create_error = std::string("qfdtd_gram_matrix_noalloc: scratch address: ") + hipGetErrorString(e);
+      return QFDTD_E_DEVICE;
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = (double *)g_scratch_dev[dev];
+  return QFDTD_OK;
+}
+
+}  // namespace
+
+extern "C" qfdtd_status qfdtd_gram_matrix_noalloc(const void *psi, int64_t n_sites, int32_t k, int32_t precision,
+                                                  double *G, void *hip_stream) {
+  using namespace qf;
+  if (!psi || !G) {
+    g_create_error = "qfdtd_gram_matrix_noalloc: NULL pointer";
+    return QFDTD_E_INVALID;
+  }
+  if (k < 1 || k > MAX_STATES) {
+    g_create_error = "qfdtd_gram_matrix_noalloc: k must be 1..8";
+    return QFDTD_E_INVALID;
+  }
+  if (precision != 0 && precision != 1) {
+    g_create_error = "qfdtd_gram_matrix_noalloc: precision must be 0 or 1";
+    return QFDTD_E_INVALID;
+  }
+  if (n_sites < 1 || n_sites > QFDTD_NOALLOC_MAX_SITES) {
+    g_create_error = "qfdtd_gram_matrix_noalloc: n_sites must be 1..QFDTD_NOALLOC_MAX_SITES (2^27)";
+    return QFDTD_E_INVALID;
+  }
+  double *part = nullptr;
+  qfdtd_status st = gram_scratch_ptr(&part);
+  if (st != QFDTD_OK) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t n = (size_t)n_sites;
+  const int nb = red_blocks(n);
+#define GF_(K)                                                                                                 \
+  if (precision) hipLaunchKernelGGL((k_gram_flat<double, K>), dim3(nb), dim3(RED_THREADS), 0, s, (const double2 *)psi, n, nb, part); \
+  else hipLaunchKernelGGL((k_gram_flat<float, K>), dim3(nb), dim3(RED_THREADS), 0, s, (const float2 *)psi, n, nb, part);
+  QF_KS_SWITCH(k, GF_)
+#undef GF_
+  hipLaunchKernelGGL(k_gram_full, dim3(1), dim3(RED_THREADS), 0, s, (const double *)part, nb, (int)k, G);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_create_error = std::string("qfdtd_gram_matrix_noalloc: kernel launch: ") + hipGetErrorString(e);
+    return QFDTD_E_DEVICE;
+  }
+  return QFDTD_OK;
+}

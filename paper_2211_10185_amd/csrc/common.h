@@ -104,6 +104,15 @@ constexpr int MAX_STATES = 8;
 constexpr int MAX_PAIRS = MAX_STATES * (MAX_STATES + 1) / 2;
 constexpr int MAX_LAUNCH = 64;       // members per launch list
 
+// Blocks of an FP64 reduction sweep over n sites: one per 2048 sites, at most MAX_RED_BLOCKS.
+// The grid, and with it the order of every FP64 sum, depends only on the site count.
+constexpr int MAX_RED_BLOCKS = 1024;
+__host__ __device__ inline int red_blocks(size_t n) {
+  size_t b = (n + 2047) / 2048;
+  if (b > (size_t)MAX_RED_BLOCKS) b = MAX_RED_BLOCKS;
+  return b < 1 ? 1 : (int)b;
+}
+
 // Kinetic kinds (eqs. HK0..HK3)
 enum { KIN_FDTD = 0, KIN_P2 = 1, KIN_SIN2 = 2, KIN_REL = 3 };
 

@@ -968,9 +968,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   c->pencil_v = (o.flags & QFDTD_F_SPLIT_NARROW) ? 1 : 0;
   c->plane = c->fft() && g_fft[N].plane[c->dbl ? 1 : 0] != nullptr && !(o.flags & QFDTD_F_ROWCOL) && !c->split;
   c->plane64 = c->fft() && g_fft[N].plane[1] != nullptr;
-  c->nblk_red = (int)((n3 + 2047) / 2048);
-  if (c->nblk_red > 1024) c->nblk_red = 1024;
-  if (c->nblk_red < 1) c->nblk_red = 1;
+  c->nblk_red = red_blocks(n3);
   c->trace_on = o.trace_energies ? 1 : 0;
   c->graphs = !(o.flags & QFDTD_F_NO_GRAPH);
   c->stencil2 = !c->fft() && !c->dbl && !(o.flags & QFDTD_F_STENCIL_1STEP);
