@@ -177,6 +177,15 @@ qfdtd_status qfdtd_set_state(qfdtd_ctx *c, int32_t i, const double *psi);
  * complex128, interleaved, N^3 elements).  Stream-ordered; no synchronisation. */
 qfdtd_status qfdtd_set_state_device(qfdtd_ctx *c, int32_t i, const void *psi_dev);
 
+/* Replace state i with seeded complex Gaussian noise generated on the device (Re and Im
+ * independent N(0, 1) per site): Philox4x32-10 (Salmon et al., SC 2011) with counter
+ * (x mod 2^32, x div 2^32, i, 0) for site x in C order and key (seed mod 2^32, seed div 2^32);
+ * the four words give u1 = ((w0 2^21 + w1 div 2^11) + 1) 2^-53 and u2 likewise from w2, w3, and
+ * the Box-Muller transform sqrt(-2 ln u1) (cos 2 pi u2 + i sin 2 pi u2) in FP64, stored in the
+ * state precision.  A random initial guess without a host array (Sec. 2: any start with a
+ * ground-state component converges).  Stream-ordered; no synchronisation. */
+qfdtd_status qfdtd_set_state_noise(qfdtd_ctx *c, int32_t i, uint64_t seed);
+
 /* Advance all k states by `steps` imaginary-time steps of size dt (Sec. 2, eq.
  * (eq_iterat)), orthonormalising every K steps and after the last one.  Enqueued on
  * the stream; returns without waiting, except that a NaN/Inf found by an earlier

@@ -72,6 +72,7 @@ _sig = {
                                 ct.POINTER(Potential), ct.POINTER(Options)]),
     "qfdtd_set_state": (ct.c_int, [P, ct.c_int32, DP]),
     "qfdtd_set_state_device": (ct.c_int, [P, ct.c_int32, P]),
+    "qfdtd_set_state_noise": (ct.c_int, [P, ct.c_int32, ct.c_uint64]),
     "qfdtd_evolve": (ct.c_int, [P, ct.c_int64, ct.c_double]),
     "qfdtd_states": (ct.c_int, [P, ct.c_int32, DP, DP]),
     "qfdtd_states_device": (ct.c_int, [P, ct.c_int32, DP, P]),

@@ -864,6 +864,41 @@ __global__ void __launch_bounds__(RED_THREADS) k_energy_finalize(const LaunchLis
 }
 
 // host <-> state conversions through an FP64 staging buffer
+// Seeded complex Gaussian noise for an initial state: Philox4x32-10 (Salmon, Moraes, Dror and
+// Shaw, SC 2011), counter (x mod 2^32, x div 2^32, slot, 0) for site x, key (seed lo, seed hi);
+// two 53-bit uniforms in (0, 1] from the four words, Box-Muller in FP64, stored in the state
+// precision.
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = (uint32_t)p1;
+    c[2] = n2;
+    c[3] = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+template <typename T>
+__global__ void k_noise(C<T> *dst, size_t n, uint32_t k0, uint32_t k1, uint32_t slot) {
+  const size_t x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  uint32_t c[4] = {(uint32_t)x, (uint32_t)(x >> 32), slot, 0u};
+  philox4x32_10(c, k0, k1);
+  const uint64_t a = (((uint64_t)c[0] << 21) | (c[1] >> 11)) + 1;
+  const uint64_t b = (((uint64_t)c[2] << 21) | (c[3] >> 11)) + 1;
+  const double u1 = (double)a * 0x1p-53, u2 = (double)b * 0x1p-53;
+  const double r = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  dst[x] = mkc<T>((T)(r * cs), (T)(r * sn));
+}
+
 template <typename T>
 __global__ void k_from64_slot(C<T> *dst, const double2 *src, size_t n) {
   const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -901,6 +936,12 @@ void launch_dt_tables(bool dbl, const double *v64, int vcomplex, int N, double d
   else
     hipLaunchKernelGGL(k_dt_tables<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v64, vcomplex, N3, dt,
                        vtab, hfac, h2fac, (float *)ktab, ksym64, N, kin, scheme);
+}
+void launch_noise(bool dbl, void *dst, size_t n, uint64_t seed, int slot, hipStream_t st) {
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  if (dbl) hipLaunchKernelGGL(k_noise<double>, g, b, 0, st, (double2 *)dst, n, k0, k1, (uint32_t)slot);
+  else hipLaunchKernelGGL(k_noise<float>, g, b, 0, st, (float2 *)dst, n, k0, k1, (uint32_t)slot);
 }
 void launch_from64_slot(bool dbl, void *dst, const double2 *src, size_t n, hipStream_t st) {
   if (dbl) hipLaunchKernelGGL(k_from64_slot<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (double2 *)dst, src, n);

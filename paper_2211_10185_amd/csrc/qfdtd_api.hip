@@ -36,6 +36,7 @@ void launch_potential(double *v64, int vcomplex, int N, double a, int kind, cons
 void launch_dt_tables(bool dbl, const double *v64, int vcomplex, int N, double dt, void *vtab, void *hfac, void *h2fac,
                       void *ktab, const double *ksym64, int kin, int scheme, hipStream_t st);
 void launch_from64_slot(bool dbl, void *dst, const double2 *src, size_t n, hipStream_t st);
+void launch_noise(bool dbl, void *dst, size_t n, uint64_t seed, int slot, hipStream_t st);
 void launch_to64_slot(bool dbl, double2 *dst, const void *src, size_t n, hipStream_t st);
 int ew_tiles_host(long long n);
 int stencil_tiles_host(int N, int k);
@@ -1118,6 +1119,22 @@ qfdtd_status qfdtd_set_state(qfdtd_ctx *c, int32_t i, const double *psi) {
   launch_from64_slot(c->dbl, (char *)c->psi + (size_t)i * n3 * c->csz(), c->scratch64, n3, c->st);
   QF_LAUNCHED(c);
   QF_HIP(c, hipStreamSynchronize(c->st));
+  c->set_mask |= 1u << i;
+  c->fresh = true;
+  const uint32_t all = (1u << c->k) - 1u;
+  if ((c->set_mask & all) == all && c->poisoned) {
+    c->poisoned = false;
+    QF_HIP(c, hipMemsetAsync(c->energy + 2 * MAX_STATES, 0, 8, c->st));
+  }
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_set_state_noise(qfdtd_ctx *c, int32_t i, uint64_t seed) {
+  if (!c) return fail(nullptr, QFDTD_E_INVALID, "ctx is NULL");
+  if (i < 0 || i >= c->k) return fail(c, QFDTD_E_INVALID, "state index out of range");
+  QF_TRY(check_status(c, false));
+  launch_noise(c->dbl, (char *)c->psi + (size_t)i * c->n3() * c->csz(), c->n3(), seed, i, c->st);
+  QF_LAUNCHED(c);
   c->set_mask |= 1u << i;
   c->fresh = true;
   const uint32_t all = (1u << c->k) - 1u;

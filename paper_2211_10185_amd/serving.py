@@ -61,11 +61,14 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
           max_slots: int = 64, tol: float = 1e-8, max_steps: int = 50000, chunk: Optional[int] = None,
           keep_psi: bool = False, realtime: bool = True,
           clock: Callable[[], float] = time.perf_counter,
-          should_cancel: Optional[Callable[[int], bool]] = None) -> dict:
+          should_cancel: Optional[Callable[[int], bool]] = None, init: str = "host") -> dict:
     """Serve ``requests`` (objects with .rid, .arrival (s), .problem); return results and stats.
 
     ``realtime``: admit a request only once the wall clock has passed its arrival
     time; otherwise every request counts as arrived at t = 0 (a closed backlog).
+    ``init``: "host" starts each solve from the problem's seeded host noise
+    (``Problem.init_states``, uploaded); "device" from the library's seeded device noise
+    (``qfdtd_set_state_noise`` with the problem's seed), with no host array.
     """
     import torch
     if budget_bytes is None:
@@ -78,6 +81,9 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
     peak_used = 0
     peak_active = 0
     chunks = 0
+    # host time per part of the loop: admission (context creation and state upload), launching a
+    # chunk, waiting for and reading the energies, retiring
+    tpart = {"admit": 0.0, "launch": 0.0, "energies": 0.0, "retire": 0.0}
     t0 = clock()
 
     def now():
@@ -92,9 +98,11 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
             if used + fp > budget_bytes and active:
                 break
             req = pending.pop(0)
+            ta = clock()
             sv = S.Solver.from_problem(p, precision=precision)
-            sv.set_states(p.init_states())
+            _init(sv, p, init)
             active.append(_Active(req, sv, fp, now()))
+            tpart["admit"] += clock() - ta
             used += fp
         peak_used = max(peak_used, used)
         peak_active = max(peak_active, len(active))
@@ -117,8 +125,10 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
                 continue
         K = chunk or active[0].req.problem.measure_every
         dts = [a.req.problem.dt for a in active]
+        tl = clock()
         try:
             S.batch_evolve([a.solver for a in active], K, dts)
+            tpart["launch"] += clock() - tl
         except L.QfdtdError:
             # a member failed in an earlier chunk: batch_evolve checks every member before it
             # launches anything, so no solve advanced; retire the failed one(s) and go on
@@ -134,8 +144,10 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
                 raise
             active = keep
             continue
+        te = clock()
         try:
             E = list(S.batch_energies([a.solver for a in active])[:, 0])
+            tpart["energies"] += clock() - te
         except L.QfdtdError:
             # every member advanced K steps; read them one by one (the same FP64 reductions, so
             # the same bits) and mark the failed one(s)
@@ -147,6 +159,7 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
                     E.append(err)
         chunks += 1
         keep = []
+        tr = clock()
         for a, e in zip(active, E):
             a.steps += K
             if isinstance(e, L.QfdtdError):
@@ -164,6 +177,7 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
                 a.prev = complex(e)
                 keep.append(a)
         active = keep
+        tpart["retire"] += clock() - tr
     makespan = now()
     ok = [r for r in done if r.status == "ok"]
     lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
@@ -176,7 +190,7 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
             # admission -> completion (time on the device, without queueing)
             "service_p50_s": float(np.percentile(svc, 50)), "service_p99_s": float(np.percentile(svc, 99)),
             "peak_active": peak_active, "peak_footprint_bytes": peak_used, "budget_bytes": budget_bytes,
-            "chunks": chunks}
+            "chunks": chunks, "host_time_s": {k: round(v, 3) for k, v in tpart.items()}}
 
 
 def _retire(a: _Active, e, conv: bool, realtime: bool, t: float, status: str, error: str) -> Result:
@@ -186,13 +200,22 @@ def _retire(a: _Active, e, conv: bool, realtime: bool, t: float, status: str, er
                   a.req.arrival if realtime else 0.0, a.t_admit, t, None, status, error)
 
 
+def _init(sv, p, init: str):
+    if init == "device":
+        sv.set_states_noise(p.seed)
+    elif init == "host":
+        sv.set_states(p.init_states())
+    else:
+        raise ValueError("init must be 'host' or 'device'")
+
+
 def solve_alone(req, precision: int = S.C64, tol: float = 1e-8, max_steps: int = 50000,
-                chunk: Optional[int] = None, keep_psi: bool = False) -> Result:
+                chunk: Optional[int] = None, keep_psi: bool = False, init: str = "host") -> Result:
     """The plain single-solve path: one request on its own, same stopping rule."""
     p = req.problem
     t0 = time.perf_counter()
     sv = S.Solver.from_problem(p, precision=precision)
-    sv.set_states(p.init_states())
+    _init(sv, p, init)
     K = chunk or p.measure_every
     prev, steps, conv, e = None, 0, False, None
     while steps < max_steps:

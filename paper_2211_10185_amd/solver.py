@@ -157,6 +157,11 @@ class Solver:
         for i in range(self.k):
             self.set_state(i, psis[i])
 
+    def set_states_noise(self, seed: int):
+        """Every state from the library's seeded device noise (stream-ordered, no host array)."""
+        for i in range(self.k):
+            self._c(L.lib.qfdtd_set_state_noise(self._ctx, i, int(seed) & 0xFFFFFFFFFFFFFFFF))
+
     def evolve(self, steps: int, dt: float):
         self._c(L.lib.qfdtd_evolve(self._ctx, int(steps), float(dt)))
 

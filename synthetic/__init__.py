@@ -82,6 +82,49 @@ def initial_states(N: int, k: int, seed: int) -> np.ndarray:
     return out
 
 
+# Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+# SC 2011): a counter-based generator.  Ten rounds of two 32 x 32 -> 64-bit multiplies; the
+# key is bumped by two Weyl constants between rounds.
+PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Philox4x32-10 of counters (arrays or scalars of uint32 values) under key (k0, k1);
+    returns the four output words as uint64 arrays holding 32-bit values."""
+    m = np.uint64(0xFFFFFFFF)
+    c = [np.asarray(x, dtype=np.uint64) & m for x in (c0, c1, c2, c3)]
+    k0, k1 = np.uint64(k0) & m, np.uint64(k1) & m
+    for _ in range(10):
+        p0 = np.uint64(PHILOX_M0) * c[0]
+        p1 = np.uint64(PHILOX_M1) * c[2]
+        c = [((p1 >> np.uint64(32)) ^ c[1] ^ k0) & m, p1 & m, ((p0 >> np.uint64(32)) ^ c[3] ^ k1) & m, p0 & m]
+        k0 = (k0 + np.uint64(PHILOX_W0)) & m
+        k1 = (k1 + np.uint64(PHILOX_W1)) & m
+    return c
+
+
+def philox_noise_states(N: int, k: int, seed: int) -> np.ndarray:
+    """k complex Gaussian-noise wavefunctions [k, N, N, N] from Philox4x32-10, the same numbers as
+    the library's qfdtd_set_state_noise: site x (C order) of state i uses counter
+    (x mod 2^32, x div 2^32, i, 0) and key (seed mod 2^32, seed div 2^32); the words w0..w3 give
+    u1 = ((w0 2^21 + w1 div 2^11) + 1) 2^-53 and u2 likewise from w2, w3, both in (0, 1], and
+    Re + i Im = sqrt(-2 ln u1) (cos 2 pi u2 + i sin 2 pi u2) (Box-Muller)."""
+    n3 = N * N * N
+    x = np.arange(n3, dtype=np.uint64)
+    out = np.empty((k, N, N, N), dtype=np.complex128)
+    for i in range(k):
+        w = philox4x32_10(x & np.uint64(0xFFFFFFFF), x >> np.uint64(32), np.full(n3, i, np.uint64),
+                          np.zeros(n3, np.uint64), seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+        a = ((w[0] << np.uint64(21)) | (w[1] >> np.uint64(11))) + np.uint64(1)
+        b = ((w[2] << np.uint64(21)) | (w[3] >> np.uint64(11))) + np.uint64(1)
+        u1 = a.astype(np.float64) * 2.0 ** -53
+        u2 = b.astype(np.float64) * 2.0 ** -53
+        r = np.sqrt(-2.0 * np.log(u1))
+        out[i] = (r * np.cos(2 * np.pi * u2) + 1j * r * np.sin(2 * np.pi * u2)).reshape(N, N, N)
+    return out
+
+
 def orbit_uniform_field(N: int, seed: int, lo: float, hi: float,
                         reflect_axes: Sequence[Sequence[int]] = ((0, 1), (2,))) -> np.ndarray:
     """Real field drawn U(lo, hi) once per orbit of a group of reflections.
