@@ -54,9 +54,10 @@ def parse():
                          "dft16: a batched 16-point DFT stage on the vector ALUs vs FP32 MFMA")
     ap.add_argument("--split", choices=["auto", "on", "off"], default="auto",
                     help="FFT solves: the split-x2 two-pass schedule where it exists (auto: the tuned choice)")
-    ap.add_argument("--split-variant", type=int, choices=[0, 1], default=None,
-                    help="split-x2 pencil tile: 0 = 4 x3 columns, 1 = 2 (default: the tuned choice)")
-    ap.add_argument("--requests", type=int, default=100, help="serve: number of requests in the trace")
+    ap.add_argument("--split-variant", type=int, choices=[0, 1, 2], default=None,
+                    help="split-x2 variant: 0 = 4 x3 columns per pencil tile, 1 = 2, 2 = x2 = 32 x 8 with 8 "
+                         "(default: the tuned choice)")
+    ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--batch-steps", type=int, default=5000, help="batch64: imaginary-time steps")
     return ap.parse_args()
@@ -261,8 +262,9 @@ def bench_rel256(args):
                                          "3 states in sectors P+,P+,P-_p3, dt=a/8, %d steps, complex64 states, "
                                          "FP64 reductions" % p.steps)
     out["config"]["reductions"] = "f64"
-    out["config"]["schedule"] = ("split-x2 (slab + pencil passes, %d-column pencil tiles)"
-                                 % (4 if s.schedule["split_variant"] == 0 else 2)
+    split_names = {0: "x2 = 16 x 16, 4-column pencil tiles", 1: "x2 = 16 x 16, 2-column pencil tiles",
+                   2: "x2 = 32 x 8, 8-column pencil tiles"}
+    out["config"]["schedule"] = ("split-x2 (slab + pencil passes, %s)" % split_names[s.schedule["split_variant"]]
                                  if s.schedule["split"] else "row + three column passes")
     out["roofline"]["traffic"] = traffic_from_profiles("traffic_rel256.json", CLASS_NAMES[dom])
     # algorithmic bytes per site-update: psi in and out (8 + 8 B) and the complex FP32 potential
@@ -296,9 +298,23 @@ def bench_serve(args):
     reqs = S.config5(n_requests=args.requests, rate=args.rate)
     warm = S.config5(n_requests=2, rate=args.rate, seed=999)
     serve(warm, max_steps=200, init="device")
-    out32 = serve(reqs, precision=0, init="device")
+    last = [0.0]
+
+    def report(st):
+        # a progress line on stderr every 10 s, so a long trace shows that it advances
+        if st["t"] - last[0] >= 10.0:
+            last[0] = st["t"]
+            print("serve: %d done, %d active, %d pending after %.0f s" % (st["done"], st["active"], st["pending"],
+                                                                         st["t"]), file=sys.stderr, flush=True)
+
+    out32 = serve(reqs, precision=0, init="device", progress=report)
     t0 = time.perf_counter()
-    alone64 = [solve_alone(q, precision=1, init="device") for q in reqs]
+    alone64 = []
+    for j, q in enumerate(reqs):
+        alone64.append(solve_alone(q, precision=1, init="device"))
+        if (j + 1) % 50 == 0:
+            print("FP64 single solves: %d of %d after %.0f s" % (j + 1, len(reqs), time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
     el64 = time.perf_counter() - t0
     # FP64 single-solve path on the same trace, requests served back to back in arrival order
     clock, lat64 = 0.0, []

@@ -135,7 +135,8 @@ typedef struct {
                                      so the results are bit-identical) and halves the memory
                                      traffic per step; a chunk of odd length ends with a
                                      single step. */
-#define QFDTD_F_SPLIT_X2 64u     /* FFT kinds, complex64, sizes with a split-x2 instantiation (N = 256):
+#define QFDTD_F_SPLIT_X2 64u     /* FFT kinds, complex64, sizes with a split-x2 instantiation
+                                     (N = 144, 150, 160, 162, 180, 192, 216, 240, 250, 256):
                                      the two-pass schedule.  The x2 transform is split four-step
                                      style (N = N1 N2); a slab pass holds N1 rows of one x1 plane
                                      and does the x3 transforms around the potential factor and
@@ -147,6 +148,10 @@ typedef struct {
 #define QFDTD_F_SPLIT_NARROW 128u /* with QFDTD_F_SPLIT_X2: pencil tiles of 2 x3 columns instead of 4
                                      (half the on-chip memory per tile, so two tiles share a
                                      compute unit; schedule autotuning) */
+#define QFDTD_F_SPLIT_WIDE 256u   /* with QFDTD_F_SPLIT_X2, N = 256: x2 = 32 x 8 with pencil tiles
+                                     of 8 x3 columns (64-byte row pieces instead of 32; schedule
+                                     autotuning).  Sizes without this shape run the plain
+                                     schedule.  With QFDTD_F_SPLIT_NARROW: QFDTD_E_INVALID. */
 #define QFDTD_F_AB_SCHEME 8u      /* FFT kinds: step with the legacy update of H_K^(0) with the
                                      FFT kinetic term swapped in (Sec. 2, the update the paper
                                      keeps while changing H_K):  psi' = A psi - B dt H_K psi,
@@ -220,6 +225,14 @@ qfdtd_status qfdtd_batch_evolve(qfdtd_ctx *const *members, int32_t n, const int6
  * orthonormalisation) or as left by the last evolve.  G: host, [k][k][2] (re, im), row-major,
  * caller-owned.  Synchronises the stream.  QFDTD_E_STATE if a state is unset. */
 qfdtd_status qfdtd_gram_matrix(qfdtd_ctx *c, double *G);
+
+/* Projected norms of the current states (Sec. 1: the orthogonal projection of snapshots):
+ * r[j] = || psi_j - (projection of psi_j on the span of the earlier states of its sector) ||,
+ * the diagonal of the FP64 Cholesky factor R of the sector's Gram matrix (G = R^H R), computed
+ * on the device in a fixed summation order.  Its absolute error is about 1e-16 / r[j], so values
+ * below about 1e-8 are rounding.  r: host, k doubles, caller-owned.  Synchronises the stream;
+ * the states are not changed. */
+qfdtd_status qfdtd_gram_residuals(qfdtd_ctx *c, double *r);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid allocation): the FP64 Gram matrix of qfdtd_gram_matrix, of k

@@ -46,6 +46,7 @@ F_THREE_GROUPS = 16
 F_STENCIL_1STEP = 32
 F_SPLIT_X2 = 64
 F_SPLIT_NARROW = 128
+F_SPLIT_WIDE = 256
 
 
 class QfdtdError(RuntimeError):
@@ -80,6 +81,7 @@ _sig = {
     "qfdtd_batch_evolve": (ct.c_int, [ct.POINTER(P), ct.c_int32, ct.POINTER(ct.c_int64), DP]),
     "qfdtd_batch_energies": (ct.c_int, [ct.POINTER(P), ct.c_int32, DP]),
     "qfdtd_gram_matrix": (ct.c_int, [P, DP]),
+    "qfdtd_gram_residuals": (ct.c_int, [P, DP]),
     "qfdtd_gram_matrix_noalloc": (ct.c_int, [P, ct.c_int64, ct.c_int32, ct.c_int32, P, P]),
     "qfdtd_read_potential_ascii": (ct.c_int, [ct.c_char_p, ct.c_int32, DP]),
     "qfdtd_write_potential_ascii": (ct.c_int, [ct.c_char_p, ct.c_int32, DP]),

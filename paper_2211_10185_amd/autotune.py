@@ -6,7 +6,8 @@ step as
     available where an N^2 plane fits in LDS, or
   * the row/column schedule (x3 row pass + three column passes: 4 passes), or
   * the split-x2 schedule (slab pass + pencil pass: 2 passes), for the sizes
-    that have split-x2 kernels, with pencil tiles of 4 or 2 x3 columns,
+    that have split-x2 kernels, with pencil tiles of 4 or 2 x3 columns, and at
+    N = 256 also with x2 = 32 x 8 and tiles of 8 columns,
 and, with k >= 2 states, either carry all states through one stream or split
 them into two (or, with k >= 3, three) groups pipelined on their own streams.  ``tune`` times every candidate
 on the device with the solver's own kernels and records the fastest in a JSON
@@ -24,7 +25,9 @@ from typing import Dict, Iterable, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PLANE_LIMIT = {0: 128, 1: 96}      # largest N whose plane fits LDS (complex64 / complex128)
-SPLIT_SIZES = {0: (256,), 1: ()}   # sizes with split-x2 (slab and pencil) kernels
+# sizes with split-x2 (slab and pencil) kernels
+SPLIT_SIZES = {0: (96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192, 216, 240, 250, 256), 1: ()}
+SPLIT_WIDE_SIZES = {0: (128, 256), 1: ()}    # ... and with the 8-row, 8-column variant
 _cache: Optional[Dict[str, dict]] = None
 
 
@@ -74,14 +77,17 @@ def candidates(N: int, precision: int, k: int):
         for g in groups:
             out.append({"rowcol": rowcol, "single_stream": g == 1, "groups": g, "split": False})
     if N in SPLIT_SIZES[precision]:
-        for v in (0, 1):
+        # variant 1 (2-column tiles) differs from variant 0 only where 4 divides N
+        variants = [0] + ([1] if N % 4 == 0 else []) + ([2] if N in SPLIT_WIDE_SIZES[precision] else [])
+        for v in variants:
             out.append({"rowcol": False, "single_stream": True, "groups": 1, "split": True, "split_variant": v})
     return out
 
 
 def candidate_name(c: dict) -> str:
     if c.get("split"):
-        return "split/%dcol" % (4 if c.get("split_variant", 0) == 0 else 2)
+        v = c.get("split_variant", 0)
+        return "split32x8/8col" if v == 2 else "split/%dcol" % (4 if v == 0 else 2)
     return ("rowcol" if c["rowcol"] else "plane") + ("/1stream" if c["groups"] == 1 else "/%dstreams" % c["groups"])
 
 

@@ -646,6 +646,8 @@ __global__ void __launch_bounds__(RED_THREADS) k_gram_finalize(const LaunchList 
   for (int i = 0; i < MAX_STATES; ++i)
     for (int j = 0; j < MAX_STATES; ++j) { Rr[i][j] = Ri[i][j] = Xr[i][j] = Xi[i][j] = 0.0; }
   int bad = 0;
+  const bool residuals = L.aux[e] == 1;   // only report the diagonal of R (see below)
+  double rdiag[MAX_STATES] = {0, 0, 0, 0, 0, 0, 0, 0};
   bool done[MAX_STATES] = {false, false, false, false, false, false, false, false};
   for (int first = 0; first < KS; ++first) {
     if (done[first]) continue;
@@ -674,6 +676,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_gram_finalize(const LaunchList 
         const int l = idx[ll];
         dd -= Rr[l][j] * Rr[l][j] + Ri[l][j] * Ri[l][j];
       }
+      rdiag[j] = (dd > 0.0 && isfinite(dd)) ? sqrt(dd) : 0.0;
       if (!(gjj > 0.0) || !isfinite(gjj) || !(dd > 1e-24 * gjj) || !isfinite(dd)) { bad = 1; dd = 1.0; }
       Rr[j][j] = sqrt(dd);
       Ri[j][j] = 0.0;
@@ -694,6 +697,12 @@ __global__ void __launch_bounds__(RED_THREADS) k_gram_finalize(const LaunchList 
         Xi[i][j] = -si / Rr[i][i];
       }
     }
+  }
+  if (residuals) {
+    // R_jj = the norm of state j after projection against the earlier states of its sector
+    // (G = R^H R per sector); qfdtd_gram_residuals reads it, nothing else changes
+    for (int j = 0; j < KS; ++j) d.energy[ENERGY_RDIAG + j] = rdiag[j];
+    return;
   }
   for (int i = 0; i < KS; ++i)
     for (int j = 0; j < KS; ++j) {

@@ -103,6 +103,8 @@ constexpr int MAX_STAGES = 12;
 constexpr int MAX_STATES = 8;
 constexpr int MAX_PAIRS = MAX_STATES * (MAX_STATES + 1) / 2;
 constexpr int MAX_LAUNCH = 64;       // members per launch list
+constexpr int ENERGY_RDIAG = 2 * MAX_STATES + 8;           // offset of the Cholesky diagonal
+constexpr int ENERGY_WORDS = ENERGY_RDIAG + MAX_STATES;    // doubles in PassDesc::energy
 
 // Blocks of an FP64 reduction sweep over n sites: one per 2048 sites, at most MAX_RED_BLOCKS.
 // The grid, and with it the order of every FP64 sum, depends only on the site count.
@@ -153,7 +155,8 @@ struct PassDesc {
   double2 *scratch64;     // [k][N^3] FP64 copy for the energy transform
   double *partials;       // [2][nblk_red][MAX_PAIRS][2] FP64 reduction partials
   double *coef;           // [MAX_STATES][MAX_STATES][2] FP64 orthonormalisation coefficients
-  double *energy;         // [MAX_STATES][2] last energies; [2*MAX_STATES] status word
+  double *energy;         // [MAX_STATES][2] last energies; [2*MAX_STATES] status word;
+                          // [ENERGY_RDIAG + j] Gram-Cholesky diagonal of state j (residual mode)
   double *trace;          // [cap][k][2] energy trace (or null)
   int32_t N, k, kin, vcomplex;
   int32_t nst;
@@ -216,14 +219,14 @@ struct FftKernels {
   const void *col[2];
   size_t plane_lds[2], row_lds[2], col_lds[2];
   int plane_nt;
-  // split-x2 two-pass schedule (slab and pencil passes), where instantiated: slab by precision,
-  // pencil (complex64) by tile variant
-  const void *slab[2];
-  size_t slab_lds[2];
-  int slab_nt, split_n1;
-  const void *pencil[2];
-  size_t pencil_lds[2];
-  int pencil_nt[2], pencil_tt[2];
+  // split-x2 two-pass schedule (slab and pencil passes, complex64), where instantiated, by
+  // variant (x2 = N1 x N2 and the pencil tile width)
+  const void *slab[3];
+  size_t slab_lds[3];
+  int slab_nt[3], split_n1[3];
+  const void *pencil[3];
+  size_t pencil_lds[3];
+  int pencil_nt[3], pencil_tt[3];
 };
 
 // Multi-size transform-pass kernels of one size group (see fft_inst.hip).

@@ -732,10 +732,12 @@ __global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
 template <typename T, int N, int N1> __host__ __device__ constexpr size_t slab_lds_t() {
   return (size_t)(N1 * padded_len(N) + tw_total<T, N>() + N1) * sizeof(C<T>);
 }
-// Pencil tile in LDS: element n (x1) of line l = k2 TT + c at n PC + l.  PC = lines + 4 puts the
-// 16 lanes of one 128-byte LDS pass (4 x1 positions x 4 columns, or 8 x 2) on distinct banks
-// when the B stage writes its outputs.
-template <int N2, int TT> __host__ __device__ constexpr int pencil_pitch() { return N2 * TT + 4; }
+// Pencil tile in LDS: element n (x1) of line l = k2 TT + c at n PC + l.  PC = lines + 4 (+ 4 more
+// where that is a multiple of 32) puts the 16 lanes of one 128-byte LDS pass (4 x1 positions x 4
+// columns, or 8 x 2) on distinct banks when the B stage writes its outputs.
+template <int N2, int TT> __host__ __device__ constexpr int pencil_pitch() {
+  return N2 * TT + 4 + ((N2 * TT + 4) % 32 == 0 ? 4 : 0);
+}
 template <typename T, int N, int N2, int TT> __host__ __device__ constexpr size_t pencil_lds_t() {
   return (size_t)(N * pencil_pitch<N2, TT>() + tw_total<T, N>()) * sizeof(C<T>) + N * sizeof(T);
 }
@@ -1015,37 +1017,80 @@ __device__ __forceinline__ void pencil_body(const LaunchList &L, int e, int t, u
   }
 }
 
-// Split-x2 tile shapes per size (complex64): N1 x N2, the slab block, and the pencil variants:
-// TT x3 columns per pencil tile with PENCIL_NT threads (one (x1, column) position per thread).
-// Variant 0 holds 4 columns (144 KiB of LDS at N = 256, one tile per CU, 32-byte row pieces),
-// variant 1 holds 2 columns (77 KiB, two tiles per CU, 16-byte row pieces).
-template <int N> struct SplitShape { static constexpr bool ok = false; };
-template <> struct SplitShape<256> {
-  static constexpr bool ok = true;
-  static constexpr int N1 = 16, N2 = 16, SLAB_NT = 256;
-  static constexpr int TT[2] = {4, 2};
+// Split-x2 shapes per size and variant (complex64): x2 = N1 x N2 (N1 stride rows per slab tile,
+// N2 consecutive rows per pencil tile; both radices have register butterflies), and TT x3
+// columns per pencil tile.
+//   variant 0: the size's default N1; 4 columns where 4 divides N (144 KiB of LDS at N = 256,
+//              one tile per CU, 32-byte row pieces), else 2;
+//   variant 1: the same N1; 2 columns (77 KiB at N = 256, two tiles per CU, 16-byte pieces);
+//   variant 2 (N = 128, 256): 8 consecutive rows (x2 = 16 x 8, 32 x 8) with 8 columns
+//              (64-byte pieces; 139 KiB at N = 256).
+// A slab tile has one thread per x3 column in its A stages (256 or 128 threads); a pencil tile
+// one per (x1, column) position, at most 1024 (two positions per thread beyond).  Sizes or
+// variants without a shape (N1 = 0) have no split-x2 kernels.
+constexpr int SPLIT_VARIANTS = 3;
+__host__ __device__ constexpr int split_n1(int N, int V) {
+  if (V == 2) return N == 256 ? 32 : N == 128 ? 16 : 0;
+  switch (N) {
+    case 96: return 16;    // 16 x 6
+    case 100: return 10;   // 10 x 10
+    case 108: return 12;   // 12 x 9
+    case 120: return 12;   // 12 x 10
+    case 128: return 16;   // 16 x 8
+    case 144: return 16;   // 16 x 9
+    case 150: return 15;   // 15 x 10
+    case 160: return 16;   // 16 x 10
+    case 162: return 18;   // 18 x 9
+    case 180: return 18;   // 18 x 10
+    case 192: return 16;   // 16 x 12
+    case 216: return 18;   // 18 x 12
+    case 240: return 16;   // 16 x 15
+    case 250: return 25;   // 25 x 10
+    case 256: return 16;   // 16 x 16
+    default: return 0;
+  }
+}
+template <int N, int V> struct SplitShape {
+  static constexpr int N1 = split_n1(N, V);
+  static constexpr bool ok = N1 > 0;
+  static constexpr int N2 = ok ? N / N1 : 1;
+  static constexpr int SLAB_NT = N <= 128 ? 128 : 256;
+  static constexpr int TT = V == 2 ? 8 : (V == 0 && N % 4 == 0) ? 4 : 2;
+  static constexpr int PENCIL_NT = N * TT <= 1024 ? N * TT : 1024;
 };
-template <int N, int V> __host__ __device__ constexpr int pencil_nt() { return N * SplitShape<N>::TT[V]; }
 
 // Pencil block order: runs of consecutive x3 tiles per XCD, so that the TT-column pieces of one
 // 128-byte row segment are fetched by blocks that share an L2.
 constexpr int PENCIL_XCD_RUN = 16;
 
-template <typename T, int N>
-__global__ void __launch_bounds__(SplitShape<N>::SLAB_NT) k_slab_t(const LaunchList L) {
+template <typename T, int N, int N1, int NT>
+__global__ void __launch_bounds__(NT) k_slab_t(const LaunchList L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  using SH = SplitShape<N>;
   const int e = find_entry(L, blockIdx.x);
-  slab_body<T, N, SH::N1, SH::SLAB_NT>(L, e, blockIdx.x - L.tile_start[e], smem);
+  slab_body<T, N, N1, NT>(L, e, blockIdx.x - L.tile_start[e], smem);
 }
 
 template <typename T, int N, int V>
-__global__ void __launch_bounds__((pencil_nt<N, V>())) k_pencil_t(const LaunchList L) {
+__global__ void __launch_bounds__((SplitShape<N, V>::PENCIL_NT)) k_pencil_t(const LaunchList L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  using SH = SplitShape<N>;
+  using SH = SplitShape<N, V>;
   const int blk = xcd_block_chunked(blockIdx.x, gridDim.x, PENCIL_XCD_RUN);
   const int e = find_entry(L, blk);
-  pencil_body<T, N, SH::N2, SH::TT[V], pencil_nt<N, V>()>(L, e, blk - L.tile_start[e], smem);
+  pencil_body<T, N, SH::N2, SH::TT, SH::PENCIL_NT>(L, e, blk - L.tile_start[e], smem);
+}
+
+template <int N, int V> void register_split(FftKernels &k) {
+  if constexpr (SplitShape<N, V>::ok) {
+    using SH = SplitShape<N, V>;
+    k.slab[V] = (const void *)k_slab_t<float, N, SH::N1, SH::SLAB_NT>;
+    k.slab_nt[V] = SH::SLAB_NT;
+    k.slab_lds[V] = slab_lds_t<float, N, SH::N1>();
+    k.split_n1[V] = SH::N1;
+    k.pencil[V] = (const void *)k_pencil_t<float, N, V>;
+    k.pencil_lds[V] = pencil_lds_t<float, N, SH::N2, SH::TT>();
+    k.pencil_nt[V] = SH::PENCIL_NT;
+    k.pencil_tt[V] = SH::TT;
+  }
 }
 
 // ------------------------------------------------------------ dispatch table
@@ -1072,21 +1117,9 @@ template <int N> void register_size(FftKernels *tab) {
   k.col[1] = (const void *)k_col_t<double, N>;
   k.col_lds[0] = col_lds_t<float, N>();
   k.col_lds[1] = col_lds_t<double, N>();
-  if constexpr (SplitShape<N>::ok) {
-    using SH = SplitShape<N>;
-    k.slab[0] = (const void *)k_slab_t<float, N>;
-    k.slab_lds[0] = slab_lds_t<float, N, SH::N1>();
-    k.slab_nt = SH::SLAB_NT;
-    k.split_n1 = SH::N1;
-    k.pencil[0] = (const void *)k_pencil_t<float, N, 0>;
-    k.pencil[1] = (const void *)k_pencil_t<float, N, 1>;
-    k.pencil_lds[0] = pencil_lds_t<float, N, SH::N2, SH::TT[0]>();
-    k.pencil_lds[1] = pencil_lds_t<float, N, SH::N2, SH::TT[1]>();
-    k.pencil_nt[0] = pencil_nt<N, 0>();
-    k.pencil_nt[1] = pencil_nt<N, 1>();
-    k.pencil_tt[0] = SH::TT[0];
-    k.pencil_tt[1] = SH::TT[1];
-  }
+  register_split<N, 0>(k);
+  register_split<N, 1>(k);
+  register_split<N, 2>(k);
 }
 
 }  // namespace qf

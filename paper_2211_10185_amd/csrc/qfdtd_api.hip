@@ -129,11 +129,19 @@ hipError_t fft_table_init() {
     }
   for (int n = 0; n <= 256; ++n)
     for (int w = 0; w < 2; ++w) {
-      // (pencil entries are tile variants of complex64, not precisions)
-      const void *fs[5] = {g_fft[n].plane[w], g_fft[n].row[w], g_fft[n].col[w], g_fft[n].slab[w], g_fft[n].pencil[w]};
-      const size_t ls[5] = {g_fft[n].plane_lds[w], g_fft[n].row_lds[w], g_fft[n].col_lds[w], g_fft[n].slab_lds[w],
-                            g_fft[n].pencil_lds[w]};
-      for (int q = 0; q < 5; ++q)
+      const void *fs[3] = {g_fft[n].plane[w], g_fft[n].row[w], g_fft[n].col[w]};
+      const size_t ls[3] = {g_fft[n].plane_lds[w], g_fft[n].row_lds[w], g_fft[n].col_lds[w]};
+      for (int q = 0; q < 3; ++q)
+        if (fs[q]) {
+          hipError_t e = hipFuncSetAttribute(fs[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ls[q]);
+          if (e != hipSuccess) return e;
+        }
+    }
+  for (int n = 0; n <= 256; ++n)
+    for (int v = 0; v < 3; ++v) {
+      const void *fs[2] = {g_fft[n].slab[v], g_fft[n].pencil[v]};
+      const size_t ls[2] = {g_fft[n].slab_lds[v], g_fft[n].pencil_lds[v]};
+      for (int q = 0; q < 2; ++q)
         if (fs[q]) {
           hipError_t e = hipFuncSetAttribute(fs[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ls[q]);
           if (e != hipSuccess) return e;
@@ -183,8 +191,8 @@ int col_tiles(int N, int k, bool dbl) {
 }
 // split-x2 schedule: slab tiles (x1 plane, fast x2 digit; a tile carries every state), pencil
 // tiles (state, slow x2 frequency, x3 column block)
-int slab_tiles(int N) { return N * (N / g_fft[N].split_n1); }
-int pencil_tiles(int N, int k, int v) { return k * g_fft[N].split_n1 * (N / g_fft[N].pencil_tt[v]); }
+int slab_tiles(int N, int v) { return N * (N / g_fft[N].split_n1[v]); }
+int pencil_tiles(int N, int k, int v) { return k * g_fft[N].split_n1[v] * (N / g_fft[N].pencil_tt[v]); }
 
 }  // namespace
 
@@ -196,7 +204,7 @@ struct qfdtd_ctx {
   int sectors[MAX_STATES] = {0};
   bool any_parity = false, vcomplex = false, dbl = false, plane = false, plane64 = false;
   bool split = false;           // FFT kinds: the two-pass split-x2 schedule (slab and pencil passes)
-  int pencil_v = 0;             // split-x2: pencil tile variant (0: 4 x3 columns, 1: 2)
+  int split_v = 0;              // split-x2 variant (x2 = N1 x N2 and the pencil tile width)
   int scheme = SCHEME_SPLIT;    // FFT kinds: split-operator step or A/B update
   hipStream_t st = nullptr;
   qfdtd_alloc_fn af = nullptr;
@@ -412,8 +420,8 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
       if (f == F_PLANE) l = K.plane_lds[dbl];
       else if (f == F_ROW) l = K.row_lds[dbl];
       else if (f == F_COL) l = K.col_lds[dbl];
-      else if (f == F_SLAB) l = K.slab_lds[dbl];
-      else if (f == F_PENCIL) l = K.pencil_lds[e.c->pencil_v];
+      else if (f == F_SLAB) l = K.slab_lds[e.c->split_v];
+      else if (f == F_PENCIL) l = K.pencil_lds[e.c->split_v];
       if (l > lds) lds = l;
       if (grp >= 0 && (f == F_PLANE || f == F_ROW || f == F_COL))
         lds = g_grp_lds[grp][f == F_PLANE ? 0 : (f == F_ROW ? 1 : 2)][dbl];
@@ -422,12 +430,12 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
     L.n = (int)cnt;
     L.tile_start[cnt] = total;
     int cls = -1;
-    bool meas_copy = false;     // transforms of the FP64 measurement copy count as measurement
+    // only the pass kernels launched below with an event pair are timed; transforms of the FP64
+    // measurement copy count as measurement
+    bool meas_copy = false;
     for (size_t i = 0; i < cnt; ++i) meas_copy = meas_copy || es[base + i].which == 1;
-    if (meas_copy) cls = TC_MEAS;
-    else if (f == F_PLANE) cls = TC_PLANE;
-    else if (f == F_ROW) cls = TC_ROW;
-    else if (f == F_COL) cls = TC_COL;
+    if (f == F_PLANE || f == F_ROW || f == F_COL)
+      cls = meas_copy ? TC_MEAS : (f == F_PLANE ? TC_PLANE : f == F_ROW ? TC_ROW : TC_COL);
     else if (f == F_STENCIL || f == F_STENCIL2) cls = TC_STENCIL;
     else if (f == F_SLAB) cls = TC_SLAB;
     else if (f == F_PENCIL) cls = TC_PENCIL;
@@ -450,8 +458,8 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
       case F_PLANE: go(fplane, ntplane, lds); break;
       case F_ROW: go(frow, LINE_THREADS, lds); break;
       case F_COL: go(fcol, LINE_THREADS, lds); break;
-      case F_SLAB: go(K.slab[dbl], K.slab_nt, lds); break;
-      case F_PENCIL: go(K.pencil[c0->pencil_v], K.pencil_nt[c0->pencil_v], lds); break;
+      case F_SLAB: go(K.slab[c0->split_v], K.slab_nt[c0->split_v], lds); break;
+      case F_PENCIL: go(K.pencil[c0->split_v], K.pencil_nt[c0->split_v], lds); break;
       case F_STENCIL: go(stencil_kernel(dbl), RED_THREADS, 0); break;
       case F_STENCIL2: go(stencil2_kernel(), S2_THREADS, 0); break;
       case F_PARITY: launch_parity(L, total, dbl, st); break;
@@ -480,10 +488,10 @@ qfdtd_status run_by_k(Fam f, std::vector<Entry> &es, bool dbl) {
   return QFDTD_OK;
 }
 
-// run a single-size kernel family once per distinct N and pencil variant (split-x2 passes)
+// run a single-size kernel family once per distinct N and split variant (split-x2 passes)
 qfdtd_status run_by_size(Fam f, std::vector<Entry> &es, bool dbl) {
   std::vector<int> keys;
-  auto key_of = [&](const Entry &e) { return e.c->N * 4 + (f == F_PENCIL ? e.c->pencil_v : 0); };
+  auto key_of = [&](const Entry &e) { return e.c->N * 4 + e.c->split_v; };
   for (auto &e : es)
     if (std::find(keys.begin(), keys.end(), key_of(e)) == keys.end()) keys.push_back(key_of(e));
   for (int kk : keys) {
@@ -608,7 +616,7 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
     qfdtd_ctx *c = ms[j];
     if (!c->fft() || n[j] <= 0) continue;
     if (c->split) {
-      sl.push_back({c, 0, M_PRE | M_FWD, slab_tiles(c->N), 0});
+      sl.push_back({c, 0, M_PRE | M_FWD, slab_tiles(c->N, c->split_v), 0});
       continue;
     }
     // A/B update: the forward transform of psi goes to alt; psi stays for the combine
@@ -642,9 +650,9 @@ qfdtd_status run_chunk(std::vector<qfdtd_ctx *> &ms, std::vector<int> &n) {
       }
       const bool last = (s == n[j] - 1);
       if (c->split) {
-        pen.push_back({c, 0, M_FWD | M_KIN | M_INV, pencil_tiles(c->N, c->k, c->pencil_v), 0});
+        pen.push_back({c, 0, M_FWD | M_KIN | M_INV, pencil_tiles(c->N, c->k, c->split_v), 0});
         sl.push_back({c, 0, last ? (uint32_t)(M_INV | M_POST) : (uint32_t)(M_INV | M_MID | M_FWD),
-                      slab_tiles(c->N), 0});
+                      slab_tiles(c->N, c->split_v), 0});
         continue;
       }
       const bool ab = c->scheme == SCHEME_AB;
@@ -959,14 +967,18 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     for (size_t g = 0; g < n3; ++g)
       if (V->grid[2 * g + 1] != 0.0) { c->vcomplex = true; break; }
   }
+  if ((o.flags & QFDTD_F_SPLIT_WIDE) && (o.flags & QFDTD_F_SPLIT_NARROW)) {
+    delete c;
+    return fail(nullptr, QFDTD_E_INVALID, "QFDTD_F_SPLIT_WIDE and QFDTD_F_SPLIT_NARROW exclude each other");
+  }
   if (c->fft() && !g_fft[N].col[0]) {
     delete c;
     return fail(nullptr, QFDTD_E_UNSUPPORTED_N, "no transform kernels for this N");
   }
   c->scheme = (c->fft() && (o.flags & QFDTD_F_AB_SCHEME)) ? SCHEME_AB : SCHEME_SPLIT;
-  c->split = c->fft() && c->scheme == SCHEME_SPLIT && (o.flags & QFDTD_F_SPLIT_X2) &&
-             g_fft[N].slab[c->dbl ? 1 : 0] != nullptr;
-  c->pencil_v = (o.flags & QFDTD_F_SPLIT_NARROW) ? 1 : 0;
+  c->split_v = (o.flags & QFDTD_F_SPLIT_WIDE) ? 2 : (o.flags & QFDTD_F_SPLIT_NARROW) ? 1 : 0;
+  c->split = c->fft() && c->scheme == SCHEME_SPLIT && (o.flags & QFDTD_F_SPLIT_X2) && !c->dbl &&
+             g_fft[N].slab[c->split_v] != nullptr;
   c->plane = c->fft() && g_fft[N].plane[c->dbl ? 1 : 0] != nullptr && !(o.flags & QFDTD_F_ROWCOL) && !c->split;
   c->plane64 = c->fft() && g_fft[N].plane[1] != nullptr;
   c->nblk_red = red_blocks(n3);
@@ -1003,7 +1015,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
   c->scratch64 = (double2 *)dalloc(c, c->k * n3 * 16);
   c->partials = (double *)dalloc(c, 2 * (size_t)c->nblk_red * MAX_PAIRS * 2 * 8);
   c->coef = (double *)dalloc(c, MAX_STATES * MAX_STATES * 2 * 8);
-  c->energy = (double *)dalloc(c, (2 * MAX_STATES + 8) * 8);
+  c->energy = (double *)dalloc(c, ENERGY_WORDS * 8);
   if (c->trace_on) c->trace = (double *)dalloc(c, (size_t)c->trace_cap * c->k * 2 * 8);
   c->d_desc = (PassDesc *)dalloc(c, sizeof(c->hd));
   bool ok = c->psi && c->v64 && c->ktab && c->tw && c->tw64 && c->ksym64 && c->scratch64 && c->partials && c->coef &&
@@ -1050,6 +1062,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     }
     d_add = c->scratch64;
   }
+  (void)hipGetLastError();    // clear an error an earlier call on this thread left behind
   launch_potential(c->v64, c->vcomplex ? 1 : 0, N, a, V->kind, V->p, d_knots, nk, d_add, c->st);
   launch_tables(c->dbl, c->tw, c->tw64, c->ksym64, N, kinetic, a, m, c->st);
   hipError_t le = hipGetLastError();
@@ -1102,7 +1115,7 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     }
     if (!okg) return bail(QFDTD_E_DEVICE, "stream creation failed");
   }
-  if (upload_desc(c) != QFDTD_OK || hipMemsetAsync(c->energy, 0, (2 * MAX_STATES + 8) * 8, c->st) != hipSuccess ||
+  if (upload_desc(c) != QFDTD_OK || hipMemsetAsync(c->energy, 0, ENERGY_WORDS * 8, c->st) != hipSuccess ||
       hipStreamSynchronize(c->st) != hipSuccess)
     return bail(QFDTD_E_DEVICE, "descriptor upload");
   *out = c;
@@ -1247,6 +1260,23 @@ qfdtd_status qfdtd_gram_matrix(qfdtd_ctx *c, double *G) {
       G[2 * (j * c->k + i)] = g[2 * p];
       G[2 * (j * c->k + i) + 1] = -g[2 * p + 1];
     }
+  return QFDTD_OK;
+}
+
+qfdtd_status qfdtd_gram_residuals(qfdtd_ctx *c, double *r) {
+  if (!c || !r) return fail(c, QFDTD_E_INVALID, "NULL argument");
+  QF_TRY(check_status(c, false));
+  QF_TRY(validate_common(c));
+  std::vector<Entry> gram{{c, 0, c->cur ? (uint32_t)M_SWAP : 0u, c->nblk_red, 0}};
+  QF_TRY(run_by_k(F_GRAM, gram, c->dbl));
+  // aux = 1: the finalize kernel writes the Cholesky diagonal and leaves the orthonormalisation
+  // coefficients and the status word alone
+  std::vector<Entry> fin{{c, 0, 0u, 1, 1}};
+  QF_TRY(run_family(F_GFIN, fin, c->dbl));
+  std::vector<double> d(MAX_STATES);
+  QF_HIP(c, hipMemcpyAsync(d.data(), c->energy + ENERGY_RDIAG, MAX_STATES * 8, hipMemcpyDeviceToHost, c->st));
+  QF_HIP(c, hipStreamSynchronize(c->st));
+  std::memcpy(r, d.data(), (size_t)c->k * 8);
   return QFDTD_OK;
 }
 

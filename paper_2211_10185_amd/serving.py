@@ -61,7 +61,8 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
           max_slots: int = 64, tol: float = 1e-8, max_steps: int = 50000, chunk: Optional[int] = None,
           keep_psi: bool = False, realtime: bool = True,
           clock: Callable[[], float] = time.perf_counter,
-          should_cancel: Optional[Callable[[int], bool]] = None, init: str = "host") -> dict:
+          should_cancel: Optional[Callable[[int], bool]] = None, init: str = "host",
+          progress: Optional[Callable[[dict], None]] = None) -> dict:
     """Serve ``requests`` (objects with .rid, .arrival (s), .problem); return results and stats.
 
     ``realtime``: admit a request only once the wall clock has passed its arrival
@@ -69,6 +70,8 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
     ``init``: "host" starts each solve from the problem's seeded host noise
     (``Problem.init_states``, uploaded); "device" from the library's seeded device noise
     (``qfdtd_set_state_noise`` with the problem's seed), with no host array.
+    ``progress``: called after every chunk with the counts of finished, active and pending
+    requests and the elapsed time.
     """
     import torch
     if budget_bytes is None:
@@ -178,6 +181,8 @@ def serve(requests: Sequence, precision: int = S.C64, budget_bytes: Optional[int
                 keep.append(a)
         active = keep
         tpart["retire"] += clock() - tr
+        if progress is not None:
+            progress({"done": len(done), "active": len(active), "pending": len(pending), "t": now()})
     makespan = now()
     ok = [r for r in done if r.status == "ok"]
     lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)

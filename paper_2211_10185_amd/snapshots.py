@@ -10,9 +10,9 @@ E_i(tau) that Sec. 4 lists as future work): the minimum of E1(tau_j) over the sn
 projected norm r_j stays above a rounding floor.  The second excited state repeats this with
 the snapshots projected against phi0 and the first excited state found.
 
-Every projection, norm and energy runs on the device through the C ABI (the FP64 Gram matrix
-of qfdtd_gram_matrix gives r_j, qfdtd_states the projection and the energy); the host only
-compares numbers to pick the stationary point.
+Every projection, norm and energy runs on the device through the C ABI (qfdtd_gram_residuals
+gives r_j from the FP64 Cholesky factor of the Gram matrix, qfdtd_states the projection and the
+energy); the host only compares numbers to pick the stationary point.
 """
 from __future__ import annotations
 
@@ -39,15 +39,6 @@ def _stationary(E: np.ndarray, r: np.ndarray, floor: float) -> Optional[int]:
         if r[j] > floor and np.isfinite(E[j]) and (best is None or E[j] < E[best]):
             best = j
     return best
-
-
-def _residual(G: np.ndarray) -> float:
-    """Norm of the last state after projection against the others (Schur complement of G;
-    absolute error about 1e-16 / r)."""
-    n = G.shape[0] - 1
-    A, g = G[:n, :n], G[:n, n]
-    r2 = G[n, n].real - np.real(np.conj(g) @ np.linalg.solve(A, g))
-    return float(np.sqrt(max(r2, 0.0)))
 
 
 def extract(problem, steps: int, every: Optional[int] = None, precision: Optional[int] = None,
@@ -84,7 +75,7 @@ def extract(problem, steps: int, every: Optional[int] = None, precision: Optiona
             for i, f in enumerate(fixed):
                 h.set_state_device(i, f)
             h.set_state_device(kf, sj)
-            r[j] = _residual(h.gram())
+            r[j] = h.residuals()[kf]
             if r[j] > floor:
                 E[j] = h.energies()[kf].real
         j_st = _stationary(E, r, floor)

@@ -120,7 +120,8 @@ class Solver:
                      | (0 if graphs else L.F_NO_GRAPH) | (L.F_AB_SCHEME if self.scheme == 1 else 0)
                      | (L.F_THREE_GROUPS if int(groups) == 3 else 0)
                      | (0 if fused_stencil else L.F_STENCIL_1STEP) | (L.F_SPLIT_X2 if split else 0)
-                     | (L.F_SPLIT_NARROW if split and split_variant == 1 else 0))
+                     | (L.F_SPLIT_NARROW if split and split_variant == 1 else 0)
+                     | (L.F_SPLIT_WIDE if split and split_variant == 2 else 0))
         opt.hip_stream = ct.c_void_p(self.stream.cuda_stream)
         if self._alloc is not None:
             opt.dev_alloc = self._alloc.alloc
@@ -182,6 +183,13 @@ class Solver:
         g = np.zeros(2 * self.k * self.k, dtype=np.float64)
         self._c(L.lib.qfdtd_gram_matrix(self._ctx, g.ctypes.data_as(ct.POINTER(ct.c_double))))
         return (g[0::2] + 1j * g[1::2]).reshape(self.k, self.k)
+
+    def residuals(self) -> np.ndarray:
+        """Norm of each state after projection against the earlier states of its sector (the
+        diagonal of the device FP64 Cholesky factor of the Gram matrix)."""
+        r = np.zeros(self.k, dtype=np.float64)
+        self._c(L.lib.qfdtd_gram_residuals(self._ctx, r.ctypes.data_as(ct.POINTER(ct.c_double))))
+        return r
 
     def set_state_device(self, i: int, t):
         """State i from a contiguous device tensor in the solver's precision (stream-ordered)."""

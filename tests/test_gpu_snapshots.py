@@ -78,3 +78,26 @@ def test_snapshot_fp32_failure_beside_the_block_method():
     s.close()
     for got, ref in zip(E, (e0, e1, e2)):
         assert abs(got - ref) < 1e-5 * abs(ref), (got, ref)
+
+
+def test_gram_residuals_are_the_projected_norms():
+    # psi_0 = 2 u0, psi_1 = 0.5 u0 + 0.3 u1, psi_2 = u0 - u1 + 1e-5 u2 with orthonormal u: the norms
+    # after projection against the earlier states are 2, 0.3 and 1e-5
+    from paper_2211_10185_amd.solver import Solver
+    N = 16
+    rng = np.random.default_rng(5)
+    U, _ = np.linalg.qr(rng.standard_normal((N ** 3, 3)) + 1j * rng.standard_normal((N ** 3, 3)))
+    u = U.T.reshape(3, N, N, N)
+    states = np.stack([2 * u[0], 0.5 * u[0] + 0.3 * u[1], u[0] - u[1] + 1e-5 * u[2]])
+    p = S.Problem(N=N, a=0.5, m=1.0, kinetic=S.K_NR_SIN2, vkind=S.V_HARMONIC, vparams=(1.0,), k=3,
+                  precision=1, dt=0.01, steps=0, seed=1)
+    s = Solver.from_problem(p)
+    s.set_states(states)
+    r = s.residuals()
+    G = s.gram()
+    s.close()
+    np.testing.assert_allclose(r[:2], [2.0, 0.3], rtol=1e-12)
+    assert abs(r[2] - 1e-5) < 1e-10, r
+    # the same from the Schur complement of the Gram matrix on the host
+    r2 = G[2, 2].real - np.real(np.conj(G[:2, 2]) @ np.linalg.solve(G[:2, :2], G[:2, 2]))
+    assert abs(np.sqrt(r2) - r[2]) < 1e-10

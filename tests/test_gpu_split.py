@@ -1,4 +1,4 @@
-"""The split-x2 two-pass schedule (slab and pencil passes) at 256^3 against the oracle.
+"""The split-x2 two-pass schedule (slab and pencil passes) against the oracle.
 
 The x2 transform is split four-step style into a stride-16 part (slab pass, with the x3
 transforms around the potential factor) and a consecutive-row part (pencil pass, with the x1
@@ -21,7 +21,8 @@ def solver(p, **kw):
     return Solver.from_problem(p, **kw)
 
 
-@pytest.mark.parametrize("K,steps,variant", [(2, 4, 0), (1, 1, 0), (3, 5, 0), (2, 4, 1), (3, 5, 1)])
+@pytest.mark.parametrize("K,steps,variant", [(2, 4, 0), (1, 1, 0), (3, 5, 0), (2, 4, 1), (3, 5, 1),
+                                             (2, 4, 2), (1, 1, 2), (3, 5, 2)])
 def test_split_schedule_relativistic_cornell_256_matches_oracle(K, steps, variant):
     # complex V, parity sectors, chunks of one step and of odd length, both pencil tile widths
     p = S.config3()
@@ -57,7 +58,7 @@ def test_split_schedule_real_potential_256_matches_oracle(kind, k):
     assert np.max(wavefunction_errors(psi, ref["states"], ref["energies"])) < 1e-4
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_split_schedule_batch_and_graphs_give_the_bits_of_a_direct_solve(variant):
     from paper_2211_10185_amd.solver import batch_evolve
     p = S.config3()
@@ -87,3 +88,58 @@ def test_split_schedule_batch_and_graphs_give_the_bits_of_a_direct_solve(variant
     a.close()
     b.close()
     assert np.array_equal(Ed, Eb) and np.array_equal(pd, pb)
+
+
+SPLIT_CASES = [  # N, kinetic, potential, split variant
+    (96, S.K_REL, S.V_CORNELL, 0), (100, S.K_NR_P2, S.V_HARMONIC, 0), (108, S.K_NR_SIN2, S.V_CORNELL, 1),
+    (120, S.K_REL, S.V_HARMONIC, 0), (128, S.K_REL, S.V_CORNELL, 0), (128, S.K_NR_SIN2, S.V_CORNELL, 2),
+    (144, S.K_NR_SIN2, S.V_HARMONIC, 0), (150, S.K_REL, S.V_CORNELL, 0), (160, S.K_REL, S.V_CORNELL, 0),
+    (160, S.K_NR_P2, S.V_CORNELL, 1), (162, S.K_NR_P2, S.V_HARMONIC, 1), (180, S.K_REL, S.V_CORNELL, 0),
+    (192, S.K_NR_SIN2, S.V_CORNELL, 1), (216, S.K_REL, S.V_HARMONIC, 0), (240, S.K_REL, S.V_CORNELL, 0),
+    (250, S.K_NR_SIN2, S.V_CORNELL, 0)]
+
+
+@pytest.mark.parametrize("N,kind,vkind,variant", SPLIT_CASES)
+def test_split_schedule_every_split_size_matches_oracle(N, kind, vkind, variant):
+    # x2 = N1 x N2 with radices 6, 8, 9, 10, 12, 15, 16, 18 and 25 in the two parts; 2-column
+    # pencil tiles where 4 does not divide N; 128-thread slab tiles up to N = 128.  The slab and
+    # pencil kernels must be the ones that ran.
+    a = 0.05
+    vp = (0.4, 0.2, a / 2) if vkind == S.V_CORNELL else (1.0,)
+    p = S.Problem(N=N, a=a, m=1.5, kinetic=kind, vkind=vkind, vparams=vp, k=2,
+                  vgrid_seed=1031 if vkind == S.V_CORNELL else None, precision=S.PREC_C64,
+                  dt=a / 8, steps=3, measure_every=2, seed=N)
+    init = p.init_states()
+    print("split schedule, N", N, "kind", kind, "vkind", vkind, "variant", variant, flush=True)
+    s = solver(p, split=True, split_variant=variant)
+    s.enable_kernel_timing(1)
+    s.set_states(init)
+    s.evolve(p.steps, p.dt)
+    E, psi = s.states()
+    n_slab = s.kernel_stats(5)[0]
+    n_pencil = s.kernel_stats(6)[0]
+    s.close()
+    assert n_slab > 0 and n_pencil > 0, (n_slab, n_pencil)
+    ref = O.solve(p, init=init)
+    print("energy err", np.max(energy_errors(E, ref["energies"])), flush=True)
+    assert np.max(energy_errors(E, ref["energies"])) < 1e-5, (E, ref["energies"])
+    assert np.max(wavefunction_errors(psi, ref["states"], ref["energies"])) < 1e-4
+
+
+def test_split_wide_and_narrow_exclude_each_other():
+    # through the C ABI: the create call rejects the pair of variant flags
+    import ctypes as ct
+    import torch
+    from paper_2211_10185_amd import _lib as L
+    from paper_2211_10185_amd.solver import potential_struct
+    pot, keep = potential_struct(S.V_HARMONIC, (1.0,))
+    opt = L.Options()
+    opt.precision = 0
+    opt.n_states = 1
+    opt.measure_every = 10
+    opt.flags = L.F_SPLIT_X2 | L.F_SPLIT_NARROW | L.F_SPLIT_WIDE
+    opt.hip_stream = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ctx = ct.c_void_p()
+    st = L.lib.qfdtd_create(ct.byref(ctx), 256, 0.05, 1.0, S.K_NR_SIN2, ct.byref(pot), ct.byref(opt))
+    assert st == L.E_INVALID and not ctx.value
+    assert b"exclude" in L.lib.qfdtd_last_error(None)

@@ -105,6 +105,30 @@ def test_energy_trace_rows_per_chunk():
     assert np.max(np.abs(tr - np.array(ref)) / np.abs(np.array(ref))) < 1e-5
 
 
+def test_kernel_timing_with_measurement_leaves_no_error_behind():
+    # every class with timed launches reports them, including the FP64 measurement copy, and
+    # the timing leaves no pending HIP error that a later create or step would report
+    for kind, N, prec in [(S.K_NR_SIN2, 48, 0), (S.K_REL, 40, 0), (S.K_NR_P2, 32, 1), (S.K_FDTD, 40, 0)]:
+        print("kernel timing, kind", kind, "N", N, "prec", prec, flush=True)
+        p = prob(kind, N, prec=prec, K=5)
+        s = solver(p)
+        s.enable_kernel_timing(1)
+        s.set_states(p.init_states())
+        s.evolve(12, p.dt)
+        s.energies()
+        counts = [s.kernel_stats(c)[0] for c in range(7)]
+        s.close()
+        assert sum(counts) > 0, counts
+        if kind != S.K_FDTD and prec == 0:
+            assert counts[4] > 0, counts      # transforms of the FP64 measurement copy
+        q = prob(S.K_NR_SIN2, 32, K=5, seed=9)
+        t = solver(q)                         # a fresh create right after
+        t.set_states(q.init_states())
+        t.evolve(5, q.dt)
+        t.energies()
+        t.close()
+
+
 def test_unstable_fdtd_dt_is_rejected():
     from paper_2211_10185_amd._lib import QfdtdError, E_UNSTABLE_DT
     p = prob(S.K_FDTD, 16, k=1)
