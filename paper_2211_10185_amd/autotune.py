@@ -7,7 +7,7 @@ step as
   * the row/column schedule (x3 row pass + three column passes: 4 passes), or
   * the split-x2 schedule (slab pass + pencil pass: 2 passes), for the sizes
     that have split-x2 kernels, with pencil tiles of 4 or 2 x3 columns, and at
-    N = 256 also with x2 = 32 x 8 and tiles of 8 columns,
+    N = 128 and 256 also with 8-row tiles of 8 columns,
 and, with k >= 2 states, either carry all states through one stream or split
 them into two (or, with k >= 3, three) groups pipelined on their own streams.  ``tune`` times every candidate
 on the device with the solver's own kernels and records the fastest in a JSON
@@ -79,15 +79,19 @@ def candidates(N: int, precision: int, k: int):
     if N in SPLIT_SIZES[precision]:
         # variant 1 (2-column tiles) differs from variant 0 only where 4 divides N
         variants = [0] + ([1] if N % 4 == 0 else []) + ([2] if N in SPLIT_WIDE_SIZES[precision] else [])
+        groups = [1, 2, 3] if k >= 3 else ([1, 2] if k >= 2 else [1])
         for v in variants:
-            out.append({"rowcol": False, "single_stream": True, "groups": 1, "split": True, "split_variant": v})
+            for g in groups:
+                out.append({"rowcol": False, "single_stream": g == 1, "groups": g, "split": True,
+                            "split_variant": v})
     return out
 
 
 def candidate_name(c: dict) -> str:
     if c.get("split"):
         v = c.get("split_variant", 0)
-        return "split32x8/8col" if v == 2 else "split/%dcol" % (4 if v == 0 else 2)
+        name = "split%s/%dcol" % (("8row", 8) if v == 2 else ("", 4 if v == 0 else 2))
+        return name + ("" if c.get("groups", 1) == 1 else "/%dstreams" % c["groups"])
     return ("rowcol" if c["rowcol"] else "plane") + ("/1stream" if c["groups"] == 1 else "/%dstreams" % c["groups"])
 
 
@@ -168,6 +172,7 @@ if __name__ == "__main__":
     ap.add_argument("out", nargs="?", default=None, help="cache file to write (default: tuning.json here)")
     ap.add_argument("--steps", type=int, default=400, help="timed imaginary-time steps per run")
     ap.add_argument("--sizes", type=int, nargs="*", default=None, help="lattice sizes (default: 32..256)")
+    ap.add_argument("--precisions", type=int, nargs="*", default=[0, 1], help="0: complex64, 1: complex128")
     a = ap.parse_args()
     sizes = a.sizes or [n for n in S.smooth_even_sizes(32, 256)]
-    tune(sizes, precisions=(0, 1), states=(1, 3), steps=a.steps, path=a.out)
+    tune(sizes, precisions=a.precisions, states=(1, 3), steps=a.steps, path=a.out)

@@ -575,10 +575,12 @@ qfdtd_status energies(std::vector<qfdtd_ctx *> &ms, bool with_trace) {
 
 // ------------------------------------------------------------- one chunk
 
-// One FFT member with its states split into two groups, each group's pass
+// One FFT member with its states split into two or three groups, each group's pass
 // chain on its own stream: a group's plane pass (transform arithmetic bound)
-// overlaps the other group's column pass (memory bound).  Forked from and
-// joined to the context stream, so ordering with the caller is unchanged.
+// overlaps the other group's column pass (memory bound); with the split-x2
+// schedule a group's pencil pass (one tile per CU, its loads, transforms and
+// stores in turn) overlaps the other group's slab pass.  Forked from and joined
+// to the context stream, so ordering with the caller is unchanged.
 qfdtd_status run_chunk_grouped(qfdtd_ctx *c, int n) {
   const bool dbl = c->dbl;
   QF_HIP(c, hipEventRecord(c->ev_fork, c->st));
@@ -586,6 +588,20 @@ qfdtd_status run_chunk_grouped(qfdtd_ctx *c, int n) {
   for (int g = 0; g < c->ngroups; ++g) {
     const int which = 2 + g, kg = c->gk[g];
     hipStream_t st = c->gst[g];
+    if (c->split) {
+      const int v = c->split_v;
+      std::vector<Entry> s0{{c, which, M_PRE | M_FWD, slab_tiles(c->N, v), 0}};
+      QF_TRY(run_family(F_SLAB, s0, dbl, 0, st));
+      for (int s = 0; s < n; ++s) {
+        std::vector<Entry> pe{{c, which, M_FWD | M_KIN | M_INV, pencil_tiles(c->N, kg, v), 0}};
+        const uint32_t rs = (s == n - 1) ? (M_INV | M_POST) : (M_INV | M_MID | M_FWD);
+        std::vector<Entry> s1{{c, which, rs, slab_tiles(c->N, v), 0}};
+        QF_TRY(run_family(F_PENCIL, pe, dbl, 0, st));
+        QF_TRY(run_family(F_SLAB, s1, dbl, 0, st));
+      }
+      QF_HIP(c, hipEventRecord(c->ev_join[g], st));
+      continue;
+    }
     std::vector<Entry> pl{{c, which, M_PRE | M_FWD, plane_tiles(c->N, kg), 0}};
     QF_TRY(run_family(F_PLANE, pl, dbl, 0, st));
     for (int s = 0; s < n; ++s) {
@@ -1098,9 +1114,9 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     d.a = a; d.m = m; d.dt = 0.0; d.stencil_c = 0.0;
     d.inv_n3 = 1.0 / (double)n3;
   }
-  // state groups for the two-stream schedule (plane schedule, k >= 2)
+  // state groups for the two-stream schedule (plane or split-x2 schedule, k >= 2)
   for (int g = 0; g < MAX_GROUPS; ++g) c->hd[2 + g] = c->hd[0];
-  if (c->fft() && c->plane && c->k >= 2 && !(o.flags & QFDTD_F_SINGLE_STREAM) && !ab) {
+  if (c->fft() && (c->plane || c->split) && c->k >= 2 && !(o.flags & QFDTD_F_SINGLE_STREAM) && !ab) {
     c->ngroups = ((o.flags & QFDTD_F_THREE_GROUPS) && c->k >= 3) ? 3 : 2;
     size_t first = 0;
     bool okg = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;

@@ -347,16 +347,18 @@ def test_potential_from_ascii_file_matches_oracle(tmp_path):
         assert phase_aligned_l2(psi[j], ref["states"][j]) < 1e-9
 
 
-@pytest.mark.parametrize("N", [120, 64])
-def test_state_groups_do_not_change_the_bits(N):
+@pytest.mark.parametrize("N,split", [(120, False), (64, False), (120, True), (160, True)])
+def test_state_groups_do_not_change_the_bits(N, split):
     # one, two or three state groups on their own streams reorder launches only; every state
-    # sees the same kernels, so energies and states are bit-identical (with graphs on or off)
+    # sees the same kernels, so energies and states are bit-identical (with graphs on or off),
+    # on the plane and on the split-x2 schedule
     from paper_2211_10185_amd.solver import Solver
     p = prob(S.K_NR_SIN2, N, k=3, K=20, a=8.0 / N)
+    print("state groups, N", N, "split", split, flush=True)
     outs = []
     for g in (1, 2, 3):
         for graphs in (False, True):
-            s = solver(p, groups=g, rowcol=False, graphs=graphs)
+            s = solver(p, groups=g, rowcol=False, graphs=graphs, split=split)
             s.set_states(p.init_states())
             s.evolve(50, p.dt)
             s.evolve(50, p.dt)
