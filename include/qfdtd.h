@@ -136,7 +136,8 @@ typedef struct {
                                      traffic per step; a chunk of odd length ends with a
                                      single step. */
 #define QFDTD_F_SPLIT_X2 64u     /* FFT kinds, complex64, sizes with a split-x2 instantiation
-                                     (N = 144, 150, 160, 162, 180, 192, 216, 240, 250, 256):
+                                     (N = 96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192,
+                                     216, 240, 250, 256):
                                      the two-pass schedule.  The x2 transform is split four-step
                                      style (N = N1 N2); a slab pass holds N1 rows of one x1 plane
                                      and does the x3 transforms around the potential factor and
@@ -145,13 +146,20 @@ typedef struct {
                                      of x2 and the x1 transforms around the kinetic factor.  Two
                                      passes over the state per step instead of four (schedule
                                      autotuning; ignored with QFDTD_F_AB_SCHEME). */
-#define QFDTD_F_SPLIT_NARROW 128u /* with QFDTD_F_SPLIT_X2: pencil tiles of 2 x3 columns instead of 4
-                                     (half the on-chip memory per tile, so two tiles share a
-                                     compute unit; schedule autotuning) */
-#define QFDTD_F_SPLIT_WIDE 256u   /* with QFDTD_F_SPLIT_X2, N = 256: x2 = 32 x 8 with pencil tiles
-                                     of 8 x3 columns (64-byte row pieces instead of 32; schedule
-                                     autotuning).  Sizes without this shape run the plain
-                                     schedule.  With QFDTD_F_SPLIT_NARROW: QFDTD_E_INVALID. */
+/* Flag bits 7-8: the split-x2 variant (schedule autotuning), read as QFDTD_SPLIT_VARIANT(flags):
+ *   0: the size's default x2 = N1 x N2 with pencil tiles of 4 x3 columns (2 where 4 does not
+ *      divide N);
+ *   1 (QFDTD_F_SPLIT_NARROW): the same factors, pencil tiles of 2 columns (half the on-chip
+ *      memory per tile, so two tiles share a compute unit);
+ *   2 (QFDTD_F_SPLIT_WIDE), N = 128 and 256: 8 consecutive rows per pencil tile and 8 columns
+ *      (64-byte row pieces instead of 32);
+ *   3 (QFDTD_F_SPLIT_SWAPPED): the default factors swapped, x2 = N2 x N1 (fewer rows per slab
+ *      tile, more per pencil tile), at the sizes where they differ.
+ * A variant a size does not have runs the schedule the other flags select. */
+#define QFDTD_F_SPLIT_NARROW 128u
+#define QFDTD_F_SPLIT_WIDE 256u
+#define QFDTD_F_SPLIT_SWAPPED 384u
+#define QFDTD_SPLIT_VARIANT(flags) (((flags) >> 7) & 3u)
 #define QFDTD_F_AB_SCHEME 8u      /* FFT kinds: step with the legacy update of H_K^(0) with the
                                      FFT kinetic term swapped in (Sec. 2, the update the paper
                                      keeps while changing H_K):  psi' = A psi - B dt H_K psi,

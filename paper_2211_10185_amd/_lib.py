@@ -47,6 +47,7 @@ F_STENCIL_1STEP = 32
 F_SPLIT_X2 = 64
 F_SPLIT_NARROW = 128
 F_SPLIT_WIDE = 256
+F_SPLIT_SWAPPED = 384
 
 
 class QfdtdError(RuntimeError):

@@ -7,7 +7,8 @@ step as
   * the row/column schedule (x3 row pass + three column passes: 4 passes), or
   * the split-x2 schedule (slab pass + pencil pass: 2 passes), for the sizes
     that have split-x2 kernels, with pencil tiles of 4 or 2 x3 columns, and at
-    N = 128 and 256 also with 8-row tiles of 8 columns,
+    N = 128 and 256 also with 8-row tiles of 8 columns, and with the two factors
+    of x2 swapped (a radix-plan choice),
 and, with k >= 2 states, either carry all states through one stream or split
 them into two (or, with k >= 3, three) groups pipelined on their own streams.  ``tune`` times every candidate
 on the device with the solver's own kernels and records the fastest in a JSON
@@ -28,6 +29,7 @@ PLANE_LIMIT = {0: 128, 1: 96}      # largest N whose plane fits LDS (complex64 /
 # sizes with split-x2 (slab and pencil) kernels
 SPLIT_SIZES = {0: (96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192, 216, 240, 250, 256), 1: ()}
 SPLIT_WIDE_SIZES = {0: (128, 256), 1: ()}    # ... and with the 8-row, 8-column variant
+SPLIT_SWAPPED_SIZES = {0: (96, 108, 120, 128, 144, 150, 160, 162, 180, 192, 216, 240, 250), 1: ()}
 _cache: Optional[Dict[str, dict]] = None
 
 
@@ -78,7 +80,8 @@ def candidates(N: int, precision: int, k: int):
             out.append({"rowcol": rowcol, "single_stream": g == 1, "groups": g, "split": False})
     if N in SPLIT_SIZES[precision]:
         # variant 1 (2-column tiles) differs from variant 0 only where 4 divides N
-        variants = [0] + ([1] if N % 4 == 0 else []) + ([2] if N in SPLIT_WIDE_SIZES[precision] else [])
+        variants = ([0] + ([1] if N % 4 == 0 else []) + ([2] if N in SPLIT_WIDE_SIZES[precision] else [])
+                    + ([3] if N in SPLIT_SWAPPED_SIZES[precision] else []))
         groups = [1, 2, 3] if k >= 3 else ([1, 2] if k >= 2 else [1])
         for v in variants:
             for g in groups:
@@ -87,10 +90,11 @@ def candidates(N: int, precision: int, k: int):
     return out
 
 
-def candidate_name(c: dict) -> str:
+def candidate_name(c: dict, N: int = 256) -> str:
     if c.get("split"):
         v = c.get("split_variant", 0)
-        name = "split%s/%dcol" % (("8row", 8) if v == 2 else ("", 4 if v == 0 else 2))
+        cols = 4 if N % 4 == 0 else 2
+        name = {0: "split/%dcol" % cols, 1: "split/2col", 2: "split8row/8col", 3: "split-swapped/%dcol" % cols}[v]
         return name + ("" if c.get("groups", 1) == 1 else "/%dstreams" % c["groups"])
     return ("rowcol" if c["rowcol"] else "plane") + ("/1stream" if c["groups"] == 1 else "/%dstreams" % c["groups"])
 
@@ -138,7 +142,7 @@ def tune(sizes: Iterable[int], precisions: Iterable[int] = (0,), states: Iterabl
             for k in states:
                 times, cands = {}, {}
                 for c in candidates(N, prec, k):
-                    name = candidate_name(c)
+                    name = candidate_name(c, N)
                     cands[name] = c
                     times[name] = time_schedule(N, prec, k, c, steps)
                 best = min(times, key=times.get)

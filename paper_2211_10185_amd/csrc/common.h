@@ -221,12 +221,12 @@ struct FftKernels {
   int plane_nt;
   // split-x2 two-pass schedule (slab and pencil passes, complex64), where instantiated, by
   // variant (x2 = N1 x N2 and the pencil tile width)
-  const void *slab[3];
-  size_t slab_lds[3];
-  int slab_nt[3], split_n1[3];
-  const void *pencil[3];
-  size_t pencil_lds[3];
-  int pencil_nt[3], pencil_tt[3];
+  const void *slab[4];
+  size_t slab_lds[4];
+  int slab_nt[4], split_n1[4];
+  const void *pencil[4];
+  size_t pencil_lds[4];
+  int pencil_nt[4], pencil_tt[4];
 };
 
 // Multi-size transform-pass kernels of one size group (see fft_inst.hip).

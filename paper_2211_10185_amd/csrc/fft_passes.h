@@ -1024,13 +1024,14 @@ __device__ __forceinline__ void pencil_body(const LaunchList &L, int e, int t, u
 //              one tile per CU, 32-byte row pieces), else 2;
 //   variant 1: the same N1; 2 columns (77 KiB at N = 256, two tiles per CU, 16-byte pieces);
 //   variant 2 (N = 128, 256): 8 consecutive rows (x2 = 16 x 8, 32 x 8) with 8 columns
-//              (64-byte pieces; 139 KiB at N = 256).
+//              (64-byte pieces; 139 KiB at N = 256);
+//   variant 3: the default factors swapped (x2 = N2 x N1: fewer rows per slab tile, more per
+//              pencil tile), where they differ; columns as in variant 0.
 // A slab tile has one thread per x3 column in its A stages (256 or 128 threads); a pencil tile
 // one per (x1, column) position, at most 1024 (two positions per thread beyond).  Sizes or
 // variants without a shape (N1 = 0) have no split-x2 kernels.
-constexpr int SPLIT_VARIANTS = 3;
-__host__ __device__ constexpr int split_n1(int N, int V) {
-  if (V == 2) return N == 256 ? 32 : N == 128 ? 16 : 0;
+constexpr int SPLIT_VARIANTS = 4;
+__host__ __device__ constexpr int split_n1_default(int N) {
   switch (N) {
     case 96: return 16;    // 16 x 6
     case 100: return 10;   // 10 x 10
@@ -1050,12 +1051,18 @@ __host__ __device__ constexpr int split_n1(int N, int V) {
     default: return 0;
   }
 }
+__host__ __device__ constexpr int split_n1(int N, int V) {
+  if (V == 2) return N == 256 ? 32 : N == 128 ? 16 : 0;
+  const int n1 = split_n1_default(N);
+  if (V == 3) return (n1 > 0 && N / n1 != n1) ? N / n1 : 0;
+  return n1;
+}
 template <int N, int V> struct SplitShape {
   static constexpr int N1 = split_n1(N, V);
   static constexpr bool ok = N1 > 0;
   static constexpr int N2 = ok ? N / N1 : 1;
   static constexpr int SLAB_NT = N <= 128 ? 128 : 256;
-  static constexpr int TT = V == 2 ? 8 : (V == 0 && N % 4 == 0) ? 4 : 2;
+  static constexpr int TT = V == 2 ? 8 : ((V == 0 || V == 3) && N % 4 == 0) ? 4 : 2;
   static constexpr int PENCIL_NT = N * TT <= 1024 ? N * TT : 1024;
 };
 
@@ -1120,6 +1127,7 @@ template <int N> void register_size(FftKernels *tab) {
   register_split<N, 0>(k);
   register_split<N, 1>(k);
   register_split<N, 2>(k);
+  register_split<N, 3>(k);
 }
 
 }  // namespace qf

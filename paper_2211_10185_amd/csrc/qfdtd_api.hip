@@ -138,7 +138,7 @@ hipError_t fft_table_init() {
         }
     }
   for (int n = 0; n <= 256; ++n)
-    for (int v = 0; v < 3; ++v) {
+    for (int v = 0; v < 4; ++v) {
       const void *fs[2] = {g_fft[n].slab[v], g_fft[n].pencil[v]};
       const size_t ls[2] = {g_fft[n].slab_lds[v], g_fft[n].pencil_lds[v]};
       for (int q = 0; q < 2; ++q)
@@ -983,16 +983,12 @@ qfdtd_status qfdtd_create(qfdtd_ctx **out, int32_t N, double a, double m, int32_
     for (size_t g = 0; g < n3; ++g)
       if (V->grid[2 * g + 1] != 0.0) { c->vcomplex = true; break; }
   }
-  if ((o.flags & QFDTD_F_SPLIT_WIDE) && (o.flags & QFDTD_F_SPLIT_NARROW)) {
-    delete c;
-    return fail(nullptr, QFDTD_E_INVALID, "QFDTD_F_SPLIT_WIDE and QFDTD_F_SPLIT_NARROW exclude each other");
-  }
   if (c->fft() && !g_fft[N].col[0]) {
     delete c;
     return fail(nullptr, QFDTD_E_UNSUPPORTED_N, "no transform kernels for this N");
   }
   c->scheme = (c->fft() && (o.flags & QFDTD_F_AB_SCHEME)) ? SCHEME_AB : SCHEME_SPLIT;
-  c->split_v = (o.flags & QFDTD_F_SPLIT_WIDE) ? 2 : (o.flags & QFDTD_F_SPLIT_NARROW) ? 1 : 0;
+  c->split_v = (int)QFDTD_SPLIT_VARIANT(o.flags);
   c->split = c->fft() && c->scheme == SCHEME_SPLIT && (o.flags & QFDTD_F_SPLIT_X2) && !c->dbl &&
              g_fft[N].slab[c->split_v] != nullptr;
   c->plane = c->fft() && g_fft[N].plane[c->dbl ? 1 : 0] != nullptr && !(o.flags & QFDTD_F_ROWCOL) && !c->split;

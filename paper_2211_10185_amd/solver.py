@@ -120,8 +120,7 @@ class Solver:
                      | (0 if graphs else L.F_NO_GRAPH) | (L.F_AB_SCHEME if self.scheme == 1 else 0)
                      | (L.F_THREE_GROUPS if int(groups) == 3 else 0)
                      | (0 if fused_stencil else L.F_STENCIL_1STEP) | (L.F_SPLIT_X2 if split else 0)
-                     | (L.F_SPLIT_NARROW if split and split_variant == 1 else 0)
-                     | (L.F_SPLIT_WIDE if split and split_variant == 2 else 0))
+                     | ((split_variant & 3) << 7 if split else 0))
         opt.hip_stream = ct.c_void_p(self.stream.cuda_stream)
         if self._alloc is not None:
             opt.dev_alloc = self._alloc.alloc

@@ -96,7 +96,13 @@ SPLIT_CASES = [  # N, kinetic, potential, split variant
     (144, S.K_NR_SIN2, S.V_HARMONIC, 0), (150, S.K_REL, S.V_CORNELL, 0), (160, S.K_REL, S.V_CORNELL, 0),
     (160, S.K_NR_P2, S.V_CORNELL, 1), (162, S.K_NR_P2, S.V_HARMONIC, 1), (180, S.K_REL, S.V_CORNELL, 0),
     (192, S.K_NR_SIN2, S.V_CORNELL, 1), (216, S.K_REL, S.V_HARMONIC, 0), (240, S.K_REL, S.V_CORNELL, 0),
-    (250, S.K_NR_SIN2, S.V_CORNELL, 0)]
+    (250, S.K_NR_SIN2, S.V_CORNELL, 0),
+    # the two factors of x2 swapped
+    (96, S.K_NR_P2, S.V_CORNELL, 3), (108, S.K_REL, S.V_HARMONIC, 3), (128, S.K_REL, S.V_CORNELL, 3),
+    (144, S.K_NR_SIN2, S.V_CORNELL, 3), (150, S.K_REL, S.V_HARMONIC, 3), (160, S.K_REL, S.V_CORNELL, 3),
+    (162, S.K_NR_SIN2, S.V_CORNELL, 3), (180, S.K_NR_P2, S.V_CORNELL, 3), (192, S.K_REL, S.V_CORNELL, 3),
+    (216, S.K_NR_SIN2, S.V_HARMONIC, 3), (240, S.K_REL, S.V_CORNELL, 3), (250, S.K_REL, S.V_CORNELL, 3),
+    (120, S.K_NR_SIN2, S.V_CORNELL, 3)]
 
 
 @pytest.mark.parametrize("N,kind,vkind,variant", SPLIT_CASES)
@@ -126,20 +132,19 @@ def test_split_schedule_every_split_size_matches_oracle(N, kind, vkind, variant)
     assert np.max(wavefunction_errors(psi, ref["states"], ref["energies"])) < 1e-4
 
 
-def test_split_wide_and_narrow_exclude_each_other():
-    # through the C ABI: the create call rejects the pair of variant flags
-    import ctypes as ct
-    import torch
-    from paper_2211_10185_amd import _lib as L
-    from paper_2211_10185_amd.solver import potential_struct
-    pot, keep = potential_struct(S.V_HARMONIC, (1.0,))
-    opt = L.Options()
-    opt.precision = 0
-    opt.n_states = 1
-    opt.measure_every = 10
-    opt.flags = L.F_SPLIT_X2 | L.F_SPLIT_NARROW | L.F_SPLIT_WIDE
-    opt.hip_stream = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
-    ctx = ct.c_void_p()
-    st = L.lib.qfdtd_create(ct.byref(ctx), 256, 0.05, 1.0, S.K_NR_SIN2, ct.byref(pot), ct.byref(opt))
-    assert st == L.E_INVALID and not ctx.value
-    assert b"exclude" in L.lib.qfdtd_last_error(None)
+@pytest.mark.parametrize("N,variant", [(160, 2), (256, 3)])
+def test_split_variant_a_size_lacks_runs_the_plain_schedule(N, variant):
+    # 160 has no 8-row variant and 256 = 16 x 16 no swapped one: the create call falls back to
+    # the schedule the other flags select (row/column here), and no slab or pencil kernel runs
+    a = 0.05
+    p = S.Problem(N=N, a=a, m=1.0, kinetic=S.K_NR_SIN2, vkind=S.V_HARMONIC, vparams=(1.0,), k=1,
+                  precision=S.PREC_C64, dt=a / 8, steps=2, measure_every=2, seed=5)
+    print("split variant fallback, N", N, "variant", variant, flush=True)
+    s = solver(p, split=True, split_variant=variant, rowcol=True, groups=1)
+    s.enable_kernel_timing(1)
+    s.set_states(p.init_states())
+    s.evolve(p.steps, p.dt)
+    s.energies()
+    counts = [s.kernel_stats(c)[0] for c in range(7)]
+    s.close()
+    assert counts[5] == 0 and counts[6] == 0 and counts[1] > 0, counts
