@@ -763,7 +763,8 @@ template <typename T> struct StateBuf {
 };
 
 // Slab pass on tile (plane i1, fast x2 digit b), for each state of the member in turn, so that
-// the potential factor rows of the tile are read from HBM once for all k states.  Steady mode
+// the potential factor rows of the tile are read from HBM once for all k states (or, with the
+// entry's aux = 1, for one state per tile: k times the tiles, each reading the factor rows).  Steady mode
 // (M_INV | M_MID | M_FWD): A^-1 from HBM, inverse x3, x h^2 (fused with the last inverse and
 // first forward stages), forward x3, A to HBM.  Other modes: chunk start (M_PRE | M_FWD: x h,
 // forward x3, A), chunk end (M_INV | M_POST: A^-1, inverse x3, x h) and plain transforms.
@@ -779,6 +780,13 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
   static_assert(sizeof(T) == 4 && (size_t)N * N * N * 8 < (1ull << 31), "complex64 states below 2 GiB");
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
+  // aux 1: one state per tile (tiles of state s follow those of state s - 1), else all k states
+  int s0 = 0, s1 = d.k;
+  if (L.aux[e] == 1) {
+    s0 = t / (N * N2);
+    s1 = s0 + 1;
+    t -= s0 * (N * N2);
+  }
   const int i1 = t / N2, b = t - (t / N2) * N2;
   C<T> *buf = (C<T> *)smem;
   C<T> *tw = buf + N1 * P;
@@ -849,7 +857,7 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
         for (int r = 0; r < RM; ++r) hq[q][r] = fac(d.h2fac, site(bl, j + r * SS::NR));
       }
     }
-    for (int s = 0; s < d.k; ++s) {
+    for (int s = s0; s < s1; ++s) {
       C<T> *g = (C<T> *)d.psi + (size_t)s * N3 + voff;
       __syncthreads();     // the twiddle tables; the previous state's reads of the LDS rows
       a_inverse_to_lds(g);
@@ -878,7 +886,7 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
     return;
   }
 #ifndef QF_PROBE_NO_GENERIC
-  for (int s = 0; s < d.k; ++s) {
+  for (int s = s0; s < s1; ++s) {
     C<T> *g = (C<T> *)d.psi + (size_t)s * N3 + voff;
     __syncthreads();       // the twiddle tables; the previous state's reads of the LDS rows
     if (mode & M_INV) {
