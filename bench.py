@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: arrival rate (1/s)")
     ap.add_argument("--batch-steps", type=int, default=5000, help="batch64: imaginary-time steps")
+    ap.add_argument("--no-fp64-path", action="store_true",
+                    help="serve: skip the FP64 single-solve run of the same trace (for profiling the batched path)")
     return ap.parse_args()
 
 
@@ -85,8 +87,21 @@ def bench_batch(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     sites = sum(p.k * p.N ** 3 for p in members)
+    # after the timed region: one more chunk with every launch timed alone (HIP events attached to
+    # the launch); a batched launch is charged to its first member's context
+    for s in solvers:
+        s.enable_kernel_timing(1)
+    batch_evolve(solvers, 50, dts)
+    batch_energies(solvers)
+    torch.cuda.synchronize()
+    dom, roof = roofline_of(solvers)
+    roof["timing"] = "HIP events attached to every launch of one 50-step chunk after the timed region"
+    roof["traffic"] = traffic_from_profiles("traffic_batch64.json", CLASS_NAMES[dom])
     for s in solvers:
         s.close()
+    # algorithmic bytes per site-update: psi in and out (16 B) and the real FP32 factor shared by
+    # the 3 states of a member (4/3 B)
+    bps = 16.0 + 4.0 / 3.0
     return {"metric": "lattice site-updates/s", "value": sites * args.batch_steps / el, "unit": "site-updates/s",
             "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": 1e3 * el, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -94,7 +109,10 @@ def bench_batch(args):
                                    "3 states, %d steps, complex64 + FP64 reductions" % args.batch_steps,
                        "sites_total": sites, "sizes": sorted({p.N for p in members})},
             "solves_per_s": len(members) / el,
-            "energy_min_max": [float(np.min(E.real[:, 0])), float(np.max(E.real[:, 0]))]}
+            "energy_min_max": [float(np.min(E.real[:, 0])), float(np.max(E.real[:, 0]))],
+            "roofline": roof,
+            "path_roofline": {"bytes_per_su": round(bps, 3),
+                              "R_alg": round(sites * args.batch_steps / el * bps / (PEAK_HBM_GBS * 1e9), 4)}}
 
 
 def roofline_of(solvers):
@@ -308,6 +326,14 @@ def bench_serve(args):
                                                                          st["t"]), file=sys.stderr, flush=True)
 
     out32 = serve(reqs, precision=0, init="device", progress=report)
+    if args.no_fp64_path:
+        return {"metric": "solves/s", "value": out32["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+                "steps": 1, "warmup": 1, "ms_per_step": 1e3 * out32["makespan_s"], "higher_is_better": True,
+                "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                "config": {"workload": "Poisson serving trace, %d requests at %.0f/s (batched complex64 path "
+                                       "only)" % (args.requests, args.rate)},
+                "latency_p50_s": out32["latency_p50_s"], "latency_p99_s": out32["latency_p99_s"],
+                "chunks": out32["chunks"], "host_time_s": out32["host_time_s"]}
     t0 = time.perf_counter()
     alone64 = []
     for j, q in enumerate(reqs):

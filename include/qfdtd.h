@@ -137,7 +137,7 @@ typedef struct {
                                      single step. */
 #define QFDTD_F_SPLIT_X2 64u     /* FFT kinds, complex64, sizes with a split-x2 instantiation
                                      (N = 96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192,
-                                     216, 240, 250, 256):
+                                     200, 216, 240, 250, 256):
                                      the two-pass schedule.  The x2 transform is split four-step
                                      style (N = N1 N2); a slab pass holds N1 rows of one x1 plane
                                      and does the x3 transforms around the potential factor and

@@ -27,9 +27,9 @@ from typing import Dict, Iterable, Optional
 HERE = os.path.dirname(os.path.abspath(__file__))
 PLANE_LIMIT = {0: 128, 1: 96}      # largest N whose plane fits LDS (complex64 / complex128)
 # sizes with split-x2 (slab and pencil) kernels
-SPLIT_SIZES = {0: (96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192, 216, 240, 250, 256), 1: ()}
+SPLIT_SIZES = {0: (96, 100, 108, 120, 128, 144, 150, 160, 162, 180, 192, 200, 216, 240, 250, 256), 1: ()}
 SPLIT_WIDE_SIZES = {0: (128, 256), 1: ()}    # ... and with the 8-row, 8-column variant
-SPLIT_SWAPPED_SIZES = {0: (96, 108, 120, 128, 144, 150, 160, 162, 180, 192, 216, 240, 250), 1: ()}
+SPLIT_SWAPPED_SIZES = {0: (96, 108, 120, 128, 144, 150, 160, 162, 180, 192, 200, 216, 240, 250), 1: ()}
 _cache: Optional[Dict[str, dict]] = None
 
 
@@ -94,7 +94,7 @@ def candidate_name(c: dict, N: int = 256) -> str:
     if c.get("split"):
         v = c.get("split_variant", 0)
         cols = 4 if N % 4 == 0 else 2
-        name = {0: "split/%dcol" % cols, 1: "split/2col", 2: "split8row/8col", 3: "split-swapped/%dcol" % cols}[v]
+        name = {0: "split/%dcol" % cols, 1: "split/2col", 2: "split8row/8col", 3: "split-swapped"}[v]
         return name + ("" if c.get("groups", 1) == 1 else "/%dstreams" % c["groups"])
     return ("rowcol" if c["rowcol"] else "plane") + ("/1stream" if c["groups"] == 1 else "/%dstreams" % c["groups"])
 

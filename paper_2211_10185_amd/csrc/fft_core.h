@@ -155,7 +155,7 @@ template <bool INV, typename V> struct Dft<5, INV, V> {
   }
 };
 
-// x * e^{-+ 2 pi i m / NN} for NN = 6, 9, 10, 12, 15, 18, 25 or 32 and a compile-time m
+// x * e^{-+ 2 pi i m / NN} for NN = 6, 9, 10, 12, 15, 18, 20, 25 or 32 and a compile-time m
 // (forward sign -, inverse +).
 // The tables hold cos and sin of 2 pi m / NN to 21 digits, with the symmetries
 // cos(2 pi (NN - m)/NN) = cos(2 pi m/NN), sin(2 pi (NN - m)/NN) = -sin(2 pi m/NN) exact.
@@ -216,6 +216,14 @@ __device__ __forceinline__ V rot_root(V a) {
                                 -0.984807753012208059367, -0.642787609686539326323};
       cm = cs[m];
       sm = sn[m];
+    } else if constexpr (NN == 20) {
+      // the first quadrant; cos and sin of 2 pi m / 20 follow by the quarter-turn symmetries
+      constexpr double q[6] = {0.0, 0.309016994374947424102, 0.587785252292473129169, 0.809016994374947424102,
+                               0.951056516295153572116, 1.0};
+      constexpr int oc = m / 5, r = m % 5;       // 2 pi m / 20 = oc pi/2 + 2 pi r / 20
+      constexpr double c0 = q[5 - r], s0 = q[r];
+      cm = oc == 0 ? c0 : oc == 1 ? -s0 : oc == 2 ? -c0 : s0;
+      sm = oc == 0 ? s0 : oc == 1 ? c0 : oc == 2 ? -s0 : -c0;
     } else if constexpr (NN == 32) {
       // the first octant; cos and sin of 2 pi m / 32 follow by the quarter-turn symmetries
       constexpr double q[9] = {0.0, 0.195090322016128267848, 0.382683432365089771728, 0.555570233019602224743,
@@ -226,7 +234,7 @@ __device__ __forceinline__ V rot_root(V a) {
       cm = oc == 0 ? c0 : oc == 1 ? -s0 : oc == 2 ? -c0 : s0;
       sm = oc == 0 ? s0 : oc == 1 ? c0 : oc == 2 ? -s0 : -c0;
     } else {
-      static_assert(NN == 25, "roots of unity of order 6, 9, 10, 12, 15, 18, 25 or 32");
+      static_assert(NN == 25, "roots of unity of order 6, 9, 10, 12, 15, 18, 20, 25 or 32");
       constexpr double cs[25] = {
           1.0, 0.968583161128631119490, 0.876306680043863587308, 0.728968627421411523147,
           0.535826794978996618271, 0.309016994374947424102, 0.062790519529313376076, -0.187381314585724630543,
@@ -344,7 +352,7 @@ template <bool INV, typename V> struct Dft<18, INV, V> {
 
 // Radix A B (A, B small): DFT_A over n1 of x[B n1 + n2], twiddle w_{AB}^{n2 k1}, DFT_B over
 // n2 -> X[k1 + A k2].  Used for the two-stage complex64 plans of sizes with several small
-// factors (radices 12 = 4 x 3 and 15 = 3 x 5) and for radix 32 = 4 x 8.
+// factors (radices 12 = 4 x 3 and 15 = 3 x 5) and for radices 20 = 4 x 5 and 32 = 4 x 8.
 template <int A, int B, bool INV, typename V, int N2, int K1>
 __device__ __forceinline__ void splitab_twiddle(V (&t)[A], V (&y)[A][B]) {
   if constexpr (K1 < A) {
@@ -380,7 +388,10 @@ template <bool INV, typename V> struct Dft<12, INV, V> {
 template <bool INV, typename V> struct Dft<15, INV, V> {
   static __device__ __forceinline__ void run(V *v) { dft_splitab<3, 5, INV, V>(v); }
 };
-// 32 = 4 x 8 (the x2 part of split-x2 tiles that stride 32 rows)
+// 20 = 4 x 5 and 32 = 4 x 8 (x2 parts of split-x2 tiles)
+template <bool INV, typename V> struct Dft<20, INV, V> {
+  static __device__ __forceinline__ void run(V *v) { dft_splitab<4, 5, INV, V>(v); }
+};
 template <bool INV, typename V> struct Dft<32, INV, V> {
   static __device__ __forceinline__ void run(V *v) { dft_splitab<4, 8, INV, V>(v); }
 };

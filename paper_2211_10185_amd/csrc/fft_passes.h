@@ -1034,7 +1034,8 @@ __device__ __forceinline__ void pencil_body(const LaunchList &L, int e, int t, u
 //   variant 2 (N = 128, 256): 8 consecutive rows (x2 = 16 x 8, 32 x 8) with 8 columns
 //              (64-byte pieces; 139 KiB at N = 256);
 //   variant 3: the default factors swapped (x2 = N2 x N1: fewer rows per slab tile, more per
-//              pencil tile), where they differ; columns as in variant 0.
+//              pencil tile), where they differ; columns as in variant 0 up to 16 pencil rows,
+//              else 2.
 // A slab tile has one thread per x3 column in its A stages (256 or 128 threads); a pencil tile
 // one per (x1, column) position, at most 1024 (two positions per thread beyond).  Sizes or
 // variants without a shape (N1 = 0) have no split-x2 kernels.
@@ -1052,6 +1053,7 @@ __host__ __device__ constexpr int split_n1_default(int N) {
     case 162: return 18;   // 18 x 9
     case 180: return 18;   // 18 x 10
     case 192: return 16;   // 16 x 12
+    case 200: return 20;   // 20 x 10
     case 216: return 18;   // 18 x 12
     case 240: return 16;   // 16 x 15
     case 250: return 25;   // 25 x 10
@@ -1070,7 +1072,7 @@ template <int N, int V> struct SplitShape {
   static constexpr bool ok = N1 > 0;
   static constexpr int N2 = ok ? N / N1 : 1;
   static constexpr int SLAB_NT = N <= 128 ? 128 : 256;
-  static constexpr int TT = V == 2 ? 8 : ((V == 0 || V == 3) && N % 4 == 0) ? 4 : 2;
+  static constexpr int TT = V == 2 ? 8 : ((V == 0 || (V == 3 && N2 <= 16)) && N % 4 == 0) ? 4 : 2;
   static constexpr int PENCIL_NT = N * TT <= 1024 ? N * TT : 1024;
 };
 

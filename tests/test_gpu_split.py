@@ -102,12 +102,12 @@ SPLIT_CASES = [  # N, kinetic, potential, split variant
     (144, S.K_NR_SIN2, S.V_CORNELL, 3), (150, S.K_REL, S.V_HARMONIC, 3), (160, S.K_REL, S.V_CORNELL, 3),
     (162, S.K_NR_SIN2, S.V_CORNELL, 3), (180, S.K_NR_P2, S.V_CORNELL, 3), (192, S.K_REL, S.V_CORNELL, 3),
     (216, S.K_NR_SIN2, S.V_HARMONIC, 3), (240, S.K_REL, S.V_CORNELL, 3), (250, S.K_REL, S.V_CORNELL, 3),
-    (120, S.K_NR_SIN2, S.V_CORNELL, 3)]
+    (120, S.K_NR_SIN2, S.V_CORNELL, 3), (200, S.K_REL, S.V_CORNELL, 0), (200, S.K_NR_SIN2, S.V_HARMONIC, 3)]
 
 
 @pytest.mark.parametrize("N,kind,vkind,variant", SPLIT_CASES)
 def test_split_schedule_every_split_size_matches_oracle(N, kind, vkind, variant):
-    # x2 = N1 x N2 with radices 6, 8, 9, 10, 12, 15, 16, 18 and 25 in the two parts; 2-column
+    # x2 = N1 x N2 with radices 6, 8, 9, 10, 12, 15, 16, 18, 20 and 25 in the two parts; 2-column
     # pencil tiles where 4 does not divide N; 128-thread slab tiles up to N = 128.  The slab and
     # pencil kernels must be the ones that ran.
     a = 0.05
