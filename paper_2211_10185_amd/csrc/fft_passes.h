@@ -1078,7 +1078,7 @@ template <int N, int V> struct SplitShape {
 
 // Pencil block order: runs of consecutive x3 tiles per XCD, so that the TT-column pieces of one
 // 128-byte row segment are fetched by blocks that share an L2.
-constexpr int PENCIL_XCD_RUN = 16;
+constexpr int PENCIL_XCD_RUN = 128;
 
 template <typename T, int N, int N1, int NT>
 __global__ void __launch_bounds__(NT) k_slab_t(const LaunchList L) {
