@@ -76,11 +76,13 @@ __device__ __forceinline__ T kin_factor_t(const PassDesc &d, int i1, int i2, int
     const T p2 = kt[i1] + kt[i2] + kt[i3];
     const T m = (T)d.m;
     if constexpr (sizeof(T) == 4) {
-      // single-instruction sqrt, reciprocal and 2^x (about 1 ulp each; the
-      // factor's relative error stays far below the complex64 state's)
-      const float tk = p2 * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(p2 + m * m) + m);
-      if (d.scheme == SCHEME_AB) return tk * (float)(d.dt * d.inv_n3);
-      return __builtin_amdgcn_exp2f(-(float)d.dt * 1.4426950408889634f * tk) * (float)d.inv_n3;
+      // single-instruction sqrt, reciprocal and 2^x (about 1 ulp each).  The A/B factor is
+      // dt T itself, so T = p^2 / (sqrt(p^2 + m^2) + m) avoids the cancellation; in the split
+      // factor T only enters the exponent, where sqrt(p^2 + m^2) - m is off by at most
+      // dt sqrt(p^2 + m^2) 2^-24 in absolute terms, and the reciprocal is saved
+      const float r = __builtin_amdgcn_sqrtf(p2 + m * m);
+      if (d.scheme == SCHEME_AB) return p2 * __builtin_amdgcn_rcpf(r + m) * (float)(d.dt * d.inv_n3);
+      return __builtin_amdgcn_exp2f(-(float)d.dt * 1.4426950408889634f * (r - m)) * (float)d.inv_n3;
     } else {
       const T tk = p2 / (sqrt(p2 + m * m) + m);   // sqrt(p^2 + m^2) - m without cancellation
       if (d.scheme == SCHEME_AB) return tk * (T)(d.dt * d.inv_n3);
@@ -959,9 +961,9 @@ __device__ __forceinline__ void pencil_body(const LaunchList &L, int e, int t, u
   auto kfac = [&](int i1, int i2, int i3) -> T {
     if (rel) {
       const T p2 = ktl[i1] + ktl[i2] + ktl[i3];
-      const float tk = p2 * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(p2 + mm * mm) + mm);
-      if (ab) return tk * dtn;
-      return __builtin_amdgcn_exp2f(-dtT * 1.4426950408889634f * tk) * in3;
+      const float r = __builtin_amdgcn_sqrtf(p2 + mm * mm);
+      if (ab) return p2 * __builtin_amdgcn_rcpf(r + mm) * dtn;
+      return __builtin_amdgcn_exp2f(-dtT * 1.4426950408889634f * (r - mm)) * in3;
     }
     if (ab) return (ktl[i1] + ktl[i2] + ktl[i3]) * dtn;
     return ktl[i1] * ktl[i2] * ktl[i3] * in3;
