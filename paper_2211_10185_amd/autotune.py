@@ -15,7 +15,8 @@ on the device with the solver's own kernels and records the fastest in a JSON
 cache; ``schedule_for`` is what ``Solver`` consults at creation.
 
 Cache: ``$QFDTD_TUNING`` if set, else ``tuning.json`` next to this file.
-Entry key: "N/precision/states" with states clipped to {1, 2+}.
+Entry key: "N/precision/states" with states clipped to {1, 2+}.  An entry with a "pinned" note
+was chosen from another measurement (the note says which) and ``tune`` leaves it as it is.
 """
 from __future__ import annotations
 
@@ -140,6 +141,11 @@ def tune(sizes: Iterable[int], precisions: Iterable[int] = (0,), states: Iterabl
     for N in sizes:
         for prec in precisions:
             for k in states:
+                if entries.get(key(N, prec, k), {}).get("pinned"):
+                    # a choice made from a measurement other than this timing (the entry says which)
+                    if verbose:
+                        print("tune N=%d prec=%d k=%d: pinned, kept" % (N, prec, k), flush=True)
+                    continue
                 times, cands = {}, {}
                 for c in candidates(N, prec, k):
                     name = candidate_name(c, N)
