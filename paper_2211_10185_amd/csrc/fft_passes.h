@@ -887,7 +887,6 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
     }
     return;
   }
-#ifndef QF_PROBE_NO_GENERIC
   for (int s = s0; s < s1; ++s) {
     C<T> *g = (C<T> *)d.psi + (size_t)s * N3 + voff;
     __syncthreads();       // the twiddle tables; the previous state's reads of the LDS rows
@@ -925,7 +924,6 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
       }
     }
   }
-#endif
 }
 
 // Pencil pass on tile (state s, slow x2 frequency k1, x3 columns c0 .. c0 + TT - 1), steady
