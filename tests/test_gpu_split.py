@@ -148,3 +148,25 @@ def test_split_variant_a_size_lacks_runs_the_plain_schedule(N, variant):
     counts = [s.kernel_stats(c)[0] for c in range(7)]
     s.close()
     assert counts[5] == 0 and counts[6] == 0 and counts[1] > 0, counts
+
+
+@pytest.mark.parametrize("groups", [2, 3])
+def test_split_schedule_state_groups_with_parity_sectors_match_oracle(groups):
+    # config 3's structure at 128^3: complex V, sectors (P+, P+, P-_p3), the states split into
+    # groups with their own pass chains on their own streams, chunks of 2 steps
+    a = 0.05
+    p = S.Problem(N=128, a=a, m=1.5, kinetic=S.K_REL, vkind=S.V_CORNELL, vparams=(0.4, 0.2, a / 2), k=3,
+                  vgrid_seed=1031, sectors=(S.S_PLUS, S.S_PLUS, S.S_PK3), precision=S.PREC_C64,
+                  dt=a / 8, steps=5, measure_every=2, seed=31)
+    init = p.init_states()
+    print("split schedule, 128^3, parity sectors, groups", groups, flush=True)
+    s = solver(p, split=True, split_variant=0, groups=groups)
+    assert s.schedule["groups"] == groups
+    s.set_states(init)
+    s.evolve(p.steps, p.dt)
+    E, psi = s.states()
+    s.close()
+    ref = O.solve(p, init=init)
+    print("energy err", np.max(energy_errors(E, ref["energies"])), flush=True)
+    assert np.max(energy_errors(E, ref["energies"])) < 1e-5, (E, ref["energies"])
+    assert np.max(wavefunction_errors(psi, ref["states"], ref["energies"])) < 1e-4
