@@ -281,7 +281,7 @@ def bench_rel256(args):
                                          "FP64 reductions" % p.steps)
     out["config"]["reductions"] = "f64"
     split_names = {0: "x2 = 16 x 16, 4-column pencil tiles", 1: "x2 = 16 x 16, 2-column pencil tiles",
-                   2: "x2 = 32 x 8, 8-column pencil tiles"}
+                   2: "x2 = 32 x 8, 8-column pencil tiles", 3: "x2 factors swapped"}
     out["config"]["schedule"] = ("split-x2 (slab + pencil passes, %s)" % split_names[s.schedule["split_variant"]]
                                  if s.schedule["split"] else "row + three column passes")
     out["roofline"]["traffic"] = traffic_from_profiles("traffic_rel256.json", CLASS_NAMES[dom])
@@ -290,6 +290,13 @@ def bench_rel256(args):
     bsu = 16 + 8 / 3
     out["path_roofline"] = {"bytes_per_su": round(bsu, 3), "R_alg": round(out["value"] * bsu / (PEAK_HBM_GBS * 1e9), 4),
                             "copy_ceiling_GBps": copy_ceiling_gbs()}
+    # R_bw of the step: the counter-measured bytes of the step's two passes over their launch times
+    moved = {c: traffic_from_profiles("traffic_rel256.json", CLASS_NAMES[c]) for c in (5, 6)}
+    bc = out["roofline"]["by_class"]
+    if all(moved.values()) and all(CLASS_NAMES[c] in bc for c in moved):
+        t_step = sum(bc[CLASS_NAMES[c]]["mean_ms"] for c in moved) * 1e-3
+        out["path_roofline"]["step_traffic_bytes"] = sum(moved.values())
+        out["path_roofline"]["R_bw_step"] = round(sum(moved.values()) / t_step / (PEAK_HBM_GBS * 1e9), 4)
     out["device"] = device_record()
     if not args.no_host_io:
         # outside the timed region: the same solve with the states handed over in host memory
