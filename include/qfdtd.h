@@ -140,6 +140,8 @@ typedef struct {
                                      200, 216, 240, 250, 256):
                                      the two-pass schedule.  The x2 transform is split four-step
                                      style (N = N1 N2); a slab pass holds N1 rows of one x1 plane
+                                     (of two at N = 128, 160 and 256, whose rows the state holds
+                                     interleaved between the passes of a chunk)
                                      and does the x3 transforms around the potential factor and
                                      the stride-N2 part of x2, a pencil pass holds N2 consecutive
                                      rows of a few x3 columns over all x1 and does the other part
@@ -152,7 +154,7 @@ typedef struct {
  *   1 (QFDTD_F_SPLIT_NARROW): the same factors, pencil tiles of 2 columns (half the on-chip
  *      memory per tile, so two tiles share a compute unit);
  *   2 (QFDTD_F_SPLIT_WIDE), N = 128 and 256: 8 consecutive rows per pencil tile and 8 columns
- *      (64-byte row pieces instead of 32);
+ *      (row pieces twice as long as with 4 columns);
  *   3 (QFDTD_F_SPLIT_SWAPPED): the default factors swapped, x2 = N2 x N1 (fewer rows per slab
  *      tile, more per pencil tile), at the sizes where they differ.
  * A variant a size does not have runs the schedule the other flags select. */

@@ -223,7 +223,7 @@ struct FftKernels {
   // variant (x2 = N1 x N2 and the pencil tile width)
   const void *slab[4];
   size_t slab_lds[4];
-  int slab_nt[4], split_n1[4];
+  int slab_nt[4], split_n1[4], split_xi[4];
   const void *pencil[4];
   size_t pencil_lds[4];
   int pencil_nt[4], pencil_tt[4];

@@ -730,10 +730,29 @@ __global__ void __launch_bounds__(LINE_THREADS) k_col_t(const LaunchList L) {
 // three column passes.  Between the passes of a chunk the state is held in this split x2
 // order; the chunk's first and last slab passes take it from and return it to real space
 // in natural order.
+//
+// Plane groups.  Between the passes the XI x1 planes XI p .. XI p + XI - 1 of a group are also
+// interleaved: the memory of row r of plane XI p + j (its "row slot" j) holds columns
+// j N/XI .. (j + 1) N/XI - 1 of all XI planes of the group, column j N/XI + w / XI of plane
+// XI p + w mod XI at element w.  A pencil tile's (x1, row) piece then spans XI times the bytes of
+// its TT columns, and a slab tile, which holds the N1 rows of all planes of a group, reads and
+// writes exactly the memory of those rows in either order (the in-place chunk-edge passes that
+// convert from and to natural order touch no other tile's memory).
 
-template <typename T, int N, int N1> __host__ __device__ constexpr size_t slab_lds_t() {
-  return (size_t)(N1 * padded_len(N) + tw_total<T, N>() + N1) * sizeof(C<T>);
+template <typename T, int N, int N1, int XI> __host__ __device__ constexpr size_t slab_lds_t() {
+  return (size_t)(XI * N1 * padded_len(N) + 8 * (XI - 1) + tw_total<T, N>() + N1) * sizeof(C<T>);
 }
+// Lines of a slab tile: row a of the group's plane j is line j N1 + a, and the lines of plane j start
+// 8 j elements (64 bytes) further, so that the A stages' lanes, which alternate between the planes
+// of one column, fall on distinct LDS banks (N1 P elements is a multiple of 128 bytes at N1 = 16).
+template <int NL, int P, int N1, int XI> struct SlabGeo {
+  static constexpr int nlines = NL;
+  static constexpr bool linefast = false;
+  static __device__ __forceinline__ int at(int b, int n) {
+    if constexpr (XI == 1) return b * P + padn(n);
+    else return b * P + (b / N1) * 8 + padn(n);
+  }
+};
 // Pencil tile in LDS: element n (x1) of line l = k2 TT + c at n PC + l.  PC = lines + 4 (+ 4 more
 // where that is a multiple of 32) puts the 16 lanes of one 128-byte LDS pass (4 x1 positions x 4
 // columns, or 8 x 2) on distinct banks when the B stage writes its outputs.
@@ -748,7 +767,14 @@ template <typename T, int N, int N2, int TT> __host__ __device__ constexpr size_
 // The base goes through readfirstlane, so the compiler holds it (plus any uniform offset) in
 // scalar registers and each access needs one 32-bit offset register instead of a 64-bit address:
 // a lane keeps one access per x2 row of a split-x2 stage in flight.
-template <typename T> struct StateBuf {
+// With G the pointer is taken in the global address space and each row's uniform offset is kept in a
+// scalar register (the empty asm stops the compiler from folding it into a 64-bit vector address),
+// so the accesses can use the global forms; without G they are flat accesses.  The slab pass
+// measured faster with the global forms, the pencil pass with flat ones.
+template <typename T, bool G = false> struct StateBuf {
+  typedef __attribute__((address_space(1))) char gchar;
+  typedef T pair_t __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(1))) pair_t gelem;
   const char *base;
   __device__ __forceinline__ explicit StateBuf(const void *p) {
     const uint64_t v = (uint64_t)p;
@@ -756,89 +782,118 @@ template <typename T> struct StateBuf {
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     base = (const char *)(((uint64_t)hi << 32) | lo);
   }
+  __device__ __forceinline__ gchar *grow(uint32_t soff) const {
+    asm volatile("" : "+s"(soff));
+    return (gchar *)base + soff;
+  }
   __device__ __forceinline__ C<T> load(uint32_t voff, uint32_t soff) const {
-    return *(const C<T> *)(base + soff + voff);
+    if constexpr (G) {
+      const pair_t v = *(const gelem *)(grow(soff) + voff);
+      return mkc<T>(v.x, v.y);
+    } else {
+      return *(const C<T> *)(base + soff + voff);
+    }
   }
   __device__ __forceinline__ void store(C<T> x, uint32_t voff, uint32_t soff) const {
-    *(C<T> *)(const_cast<char *>(base) + soff + voff) = x;
+    if constexpr (G) {
+      pair_t v;
+      v.x = x.x;
+      v.y = x.y;
+      *(gelem *)(grow(soff) + voff) = v;
+    } else {
+      *(C<T> *)(const_cast<char *>(base) + soff + voff) = x;
+    }
   }
 };
 
-// Slab pass on tile (plane i1, fast x2 digit b), for each state of the member in turn, so that
+// Slab pass on tile (plane group p, fast x2 digit b), for each state of the member in turn, so that
 // the potential factor rows of the tile are read from HBM once for all k states (or, with the
-// entry's aux = 1, for one state per tile: k times the tiles, each reading the factor rows).  Steady mode
+// entry's aux = 1, for one state per tile: k times the tiles, each reading the factor rows).  The
+// tile's LDS holds row a of the group's plane j as line j N1 + a.  Steady mode
 // (M_INV | M_MID | M_FWD): A^-1 from HBM, inverse x3, x h^2 (fused with the last inverse and
 // first forward stages), forward x3, A to HBM.  Other modes: chunk start (M_PRE | M_FWD: x h,
-// forward x3, A), chunk end (M_INV | M_POST: A^-1, inverse x3, x h) and plain transforms.
-template <typename T, int N, int N1, int NT>
+// forward x3, A), chunk end (M_INV | M_POST: A^-1, inverse x3, x h) and plain transforms.  M_INV
+// reads the split order, M_FWD writes it; otherwise the state is read or written in natural order.
+template <typename T, int N, int N1, int NT, int XI>
 __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, unsigned char *smem) {
   constexpr int N2 = N / N1;
   constexpr int P = padded_len(N);
-  constexpr int CQ = (N + NT - 1) / NT;     // x3 columns per thread in the A stages
-  using Rows = RowsGeo<N1, P>;
+  constexpr int NR = XI * N1;               // LDS lines of a tile
+  constexpr int NH = N / XI;                // columns of each plane in one row slot
+  constexpr int NP = XI * N;                // (row slot, element) positions of one row
+  constexpr int CQ = (NP + NT - 1) / NT;    // positions per thread in the A stages
+  constexpr int TPS = (N / XI) * N2;        // tiles per state
+  using Rows = SlabGeo<NR, P, N1, XI>;
   constexpr RPlan PL = plan_of<T, N, false>();
   constexpr int M = PL.n - 1;
-  static_assert(N % N1 == 0 && PL.n >= 2, "slab pass needs N1 | N and a plan of two or more stages");
+  static_assert(N % N1 == 0 && N % XI == 0 && PL.n >= 2, "slab pass needs N1 | N, XI | N and a plan of two or more stages");
   static_assert(sizeof(T) == 4 && (size_t)N * N * N * 8 < (1ull << 31), "complex64 states below 2 GiB");
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
   // aux 1: one state per tile (tiles of state s follow those of state s - 1), else all k states
   int s0 = 0, s1 = d.k;
   if (L.aux[e] == 1) {
-    s0 = t / (N * N2);
+    s0 = t / TPS;
     s1 = s0 + 1;
-    t -= s0 * (N * N2);
+    t -= s0 * TPS;
   }
-  const int i1 = t / N2, b = t - (t / N2) * N2;
-  C<T> *buf = (C<T> *)smem;
-  C<T> *tw = buf + N1 * P;
+  const int p = t / N2, b = t - (t / N2) * N2;
+  // the twiddle tables first, so that their addresses fit the LDS instructions' offset field
+  C<T> *tw = (C<T> *)smem;
   C<T> *wab = tw + tw_total<T, N>();       // W_N^{b k1}, k1 < N1: the twiddles of A
+  C<T> *buf = wab + N1;
   load_tw<T, N, NT>(tw, d);
   for (int k1 = threadIdx.x; k1 < N1; k1 += NT) wab[k1] = ((const C<T> *)d.tw)[(b * k1) % N];
   constexpr size_t N3 = (size_t)N * N * N;
-  const size_t voff = (size_t)i1 * N * N;
+  const size_t voff = (size_t)XI * p * N * N;    // the group's first plane
   const bool vc = d.vcomplex != 0;
-  auto site = [&](int a, int n) -> size_t { return (size_t)(N2 * a + b) * N + n; };
+  // offset from the group's first plane of row N2 a + b of plane (or row slot) j, element n
+  auto site = [&](int j, int a, int n) -> size_t { return ((size_t)j * N + N2 * a + b) * N + n; };
   auto fac = [&](const void *f, size_t o) -> C<T> {
     return vc ? ((const C<T> *)f)[voff + o] : mkc<T>(((const T *)f)[voff + o], 0);
   };
-  // A^-1: the N1 values of each x3 column, conj twiddles, inverse DFT over k1, rows to LDS
+  // A^-1: the N1 values of each (row slot, element) position, conj twiddles, inverse DFT over k1,
+  // to the LDS lines of the position's plane and column
   auto a_inverse_to_lds = [&](const C<T> *g) {
-    const StateBuf<T> sb(g - voff);
+    const StateBuf<T, true> sb(g);
 #pragma unroll
     for (int q = 0; q < CQ; ++q) {
-      const int col = (int)threadIdx.x + q * NT;
-      if (N % NT == 0 || col < N) {
+      const int pos = (int)threadIdx.x + q * NT;
+      if (NP % NT == 0 || pos < NP) {
+        const int j = pos / N, w = pos - (pos / N) * N;
+        const int pl = w % XI, col = j * NH + w / XI;
         C<T> v[N1];
-        const uint32_t vo = (uint32_t)((voff + site(0, col)) * sizeof(C<T>));
+        const uint32_t vo = (uint32_t)(site(j, 0, w) * sizeof(C<T>));
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) v[k1] = sb.load(vo, (uint32_t)(k1 * N2 * N * sizeof(C<T>)));
 #pragma unroll
         for (int k1 = 1; k1 < N1; ++k1) {
-          C<T> w = wab[k1];
-          w.y = -w.y;
-          v[k1] = cmul(v[k1], w);
+          C<T> w1 = wab[k1];
+          w1.y = -w1.y;
+          v[k1] = cmul(v[k1], w1);
         }
         Dft<N1, true, C<T>>::run(v);
 #pragma unroll
-        for (int a = 0; a < N1; ++a) buf[Rows::at(a, col)] = v[a];
+        for (int a = 0; a < N1; ++a) buf[Rows::at(pl * N1 + a, col)] = v[a];
       }
     }
   };
-  // A: columns from LDS rows, DFT over a, twiddles, to HBM at rows N2 k1 + b
+  // A: columns from the LDS lines, DFT over a, twiddles, to HBM at rows N2 k1 + b
   auto a_forward_from_lds = [&](C<T> *g) {
-    const StateBuf<T> sb(g - voff);
+    const StateBuf<T, true> sb(g);
 #pragma unroll
     for (int q = 0; q < CQ; ++q) {
-      const int col = (int)threadIdx.x + q * NT;
-      if (N % NT == 0 || col < N) {
+      const int pos = (int)threadIdx.x + q * NT;
+      if (NP % NT == 0 || pos < NP) {
+        const int j = pos / N, w = pos - (pos / N) * N;
+        const int pl = w % XI, col = j * NH + w / XI;
         C<T> v[N1];
 #pragma unroll
-        for (int a = 0; a < N1; ++a) v[a] = buf[Rows::at(a, col)];
+        for (int a = 0; a < N1; ++a) v[a] = buf[Rows::at(pl * N1 + a, col)];
         Dft<N1, false, C<T>>::run(v);
 #pragma unroll
         for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], wab[k1]);
-        const uint32_t vo = (uint32_t)((voff + site(0, col)) * sizeof(C<T>));
+        const uint32_t vo = (uint32_t)(site(j, 0, w) * sizeof(C<T>));
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) sb.store(v[k1], vo, (uint32_t)(k1 * N2 * N * sizeof(C<T>)));
       }
@@ -855,8 +910,9 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
       if (SS::active(q)) {
         int j, bl;
         SS::jb(q, j, bl);
+        const int pl = bl / N1, a = bl - (bl / N1) * N1;
 #pragma unroll
-        for (int r = 0; r < RM; ++r) hq[q][r] = fac(d.h2fac, site(bl, j + r * SS::NR));
+        for (int r = 0; r < RM; ++r) hq[q][r] = fac(d.h2fac, site(pl, a, j + r * SS::NR));
       }
     }
     for (int s = s0; s < s1; ++s) {
@@ -893,23 +949,25 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
     if (mode & M_INV) {
       a_inverse_to_lds(g);
     } else {
-      for (int idx = threadIdx.x; idx < N1 * N; idx += NT) {
-        const int a = idx / N, n = idx - a * N;
-        C<T> v = g[site(a, n)];
+      for (int idx = threadIdx.x; idx < NR * N; idx += NT) {
+        const int bl = idx / N, n = idx - bl * N;
+        const int pl = bl / N1, a = bl - pl * N1;
+        C<T> v = g[site(pl, a, n)];
         if (mode & M_PRE) {
-          const C<T> h = fac(d.hfac, site(a, n));
+          const C<T> h = fac(d.hfac, site(pl, a, n));
           v = vc ? cmul(v, h) : cscale(v, h.x);
         }
-        buf[Rows::at(a, n)] = v;
+        buf[Rows::at(bl, n)] = v;
       }
     }
     __syncthreads();
     if (mode & M_INV) fft_lines_t<T, N, true, Rows, NT>(buf, tw);
     if (mode & (M_MID | M_POST)) {
-      for (int idx = threadIdx.x; idx < N1 * N; idx += NT) {
-        const int a = idx / N, n = idx - a * N;
-        const C<T> h = fac((mode & M_MID) ? d.h2fac : d.hfac, site(a, n));
-        const int o = Rows::at(a, n);
+      for (int idx = threadIdx.x; idx < NR * N; idx += NT) {
+        const int bl = idx / N, n = idx - bl * N;
+        const int pl = bl / N1, a = bl - pl * N1;
+        const C<T> h = fac((mode & M_MID) ? d.h2fac : d.hfac, site(pl, a, n));
+        const int o = Rows::at(bl, n);
         buf[o] = vc ? cmul(buf[o], h) : cscale(buf[o], h.x);
       }
       __syncthreads();
@@ -918,9 +976,10 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
       fft_lines_t<T, N, false, Rows, NT>(buf, tw);
       a_forward_from_lds(g);
     } else {
-      for (int idx = threadIdx.x; idx < N1 * N; idx += NT) {
-        const int a = idx / N, n = idx - a * N;
-        g[site(a, n)] = buf[Rows::at(a, n)];
+      for (int idx = threadIdx.x; idx < NR * N; idx += NT) {
+        const int bl = idx / N, n = idx - bl * N;
+        const int pl = bl / N1, a = bl - pl * N1;
+        g[site(pl, a, n)] = buf[Rows::at(bl, n)];
       }
     }
   }
@@ -928,10 +987,11 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
 
 // Pencil pass on tile (state s, slow x2 frequency k1, x3 columns c0 .. c0 + TT - 1), steady
 // mode only (B, forward x1, x e^{-dt T(k)}/N^3, inverse x1, B^-1): the chunk's slab passes
-// bracket every pencil pass.
-template <typename T, int N, int N2, int TT, int NT>
+// bracket every pencil pass.  The state is in split order with plane groups of XI.
+template <typename T, int N, int N2, int TT, int NT, int XI>
 __device__ __forceinline__ void pencil_body(const LaunchList &L, int e, int t, unsigned char *smem) {
   constexpr int N1 = N / N2;
+  constexpr int NH = N / XI;
   constexpr int NL = N2 * TT;
   constexpr int PC = pencil_pitch<N2, TT>();
   constexpr int NCB = N / TT;
@@ -939,16 +999,18 @@ __device__ __forceinline__ void pencil_body(const LaunchList &L, int e, int t, u
   using Geo = TileGeo<NL, PC>;
   constexpr RPlan PL = plan_of<T, N, false>();
   constexpr int M = PL.n - 1;
-  static_assert(N % N2 == 0 && N % TT == 0 && PL.n >= 2, "pencil tile must divide the lattice");
+  static_assert(N % N2 == 0 && N % TT == 0 && N % XI == 0 && N % 2 == 0 && PL.n >= 2, "pencil tile must divide the lattice");
   static_assert(sizeof(T) == 4 && (size_t)N * N * N * 8 < (1ull << 31), "complex64 states below 2 GiB");
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const int cb = t % NCB;
   const int u = t / NCB;
   const int k1 = u % N1, s = u / N1;
   const int c0 = cb * TT;
-  C<T> *buf = (C<T> *)smem;
-  C<T> *tw = buf + N * PC;
+  // the twiddle and kinetic tables first, so that their addresses fit the LDS instructions'
+  // offset field
+  C<T> *tw = (C<T> *)smem;
   T *ktl = (T *)(tw + tw_total<T, N>());      // the per-axis kinetic table
+  C<T> *buf = (C<T> *)(ktl + N);
   load_tw<T, N, NT>(tw, d);
   for (int i = threadIdx.x; i < N; i += NT) ktl[i] = ((const T *)d.ktab)[i];
   constexpr size_t N3 = (size_t)N * N * N;
@@ -966,9 +1028,11 @@ __device__ __forceinline__ void pencil_body(const LaunchList &L, int e, int t, u
     if (ab) return (ktl[i1] + ktl[i2] + ktl[i3]) * dtn;
     return ktl[i1] * ktl[i2] * ktl[i3] * in3;
   };
-  // byte offset of (x1 plane i1, row N2 k1, column c0 + c); rows b apart by b N elements
+  // byte offset of (x1 plane i1, row N2 k1, column c0 + c): row slot (c0 + c) / NH of the plane
+  // group, element XI ((c0 + c) mod NH) + i1 mod XI; rows b apart by b N elements
   auto at = [&](int i1, int c) -> uint32_t {
-    return (uint32_t)(((size_t)i1 * N * N + (size_t)(N2 * k1) * N + c0 + c) * sizeof(C<T>));
+    const int col = c0 + c, j = col / NH, w = XI * (col - j * NH) + i1 % XI;
+    return (uint32_t)((((size_t)(i1 - i1 % XI + j) * N + (size_t)(N2 * k1)) * N + w) * sizeof(C<T>));
   };
   __syncthreads();       // the twiddle tables
   // B: DFT over the N2 rows of each (x1, column) position, outputs to the x1 lines (k2, c)
@@ -1026,19 +1090,20 @@ __device__ __forceinline__ void pencil_body(const LaunchList &L, int e, int t, u
 }
 
 // Split-x2 shapes per size and variant (complex64): x2 = N1 x N2 (N1 stride rows per slab tile,
-// N2 consecutive rows per pencil tile; both radices have register butterflies), and TT x3
-// columns per pencil tile.
+// N2 consecutive rows per pencil tile; both radices have register butterflies), TT x3 columns per
+// pencil tile, and plane groups of XI (split_xi).  A pencil tile's (x1, row) pieces are
+// XI TT 8 bytes.
 //   variant 0: the size's default N1; 4 columns where 4 divides N (144 KiB of LDS at N = 256,
-//              one tile per CU, 32-byte row pieces), else 2;
-//   variant 1: the same N1; 2 columns (77 KiB at N = 256, two tiles per CU, 16-byte pieces);
+//              one tile per CU), else 2;
+//   variant 1: the same N1; 2 columns (77 KiB at N = 256, two tiles per CU);
 //   variant 2 (N = 128, 256): 8 consecutive rows (x2 = 16 x 8, 32 x 8) with 8 columns
-//              (64-byte pieces; 139 KiB at N = 256);
+//              (139 KiB at N = 256);
 //   variant 3: the default factors swapped (x2 = N2 x N1: fewer rows per slab tile, more per
 //              pencil tile), where they differ; columns as in variant 0 up to 16 pencil rows,
 //              else 2.
-// A slab tile has one thread per x3 column in its A stages (256 or 128 threads); a pencil tile
-// one per (x1, column) position, at most 1024 (two positions per thread beyond).  Sizes or
-// variants without a shape (N1 = 0) have no split-x2 kernels.
+// A slab tile has one thread per (row slot, element) position in its A stages (XI times 256 or
+// 128 threads); a pencil tile one per (x1, column) position, at most 1024 (two positions per
+// thread beyond).  Sizes or variants without a shape (N1 = 0) have no split-x2 kernels.
 constexpr int SPLIT_VARIANTS = 4;
 __host__ __device__ constexpr int split_n1_default(int N) {
   switch (N) {
@@ -1067,24 +1132,31 @@ __host__ __device__ constexpr int split_n1(int N, int V) {
   if (V == 3) return (n1 > 0 && N / n1 != n1) ? N / n1 : 0;
   return n1;
 }
+// Planes per group of the split order (and per slab tile): pairs at the sizes where they measured
+// faster.  With pairs the 2-column pencil tiles read 32-byte pieces two tiles per CU, and the slab
+// tiles have twice the threads; at 192, 240 and 250 a pair tile's slab needs more than 128 VGPRs
+// (one tile per CU) and at 150 and 180 pairs measured slower.
+__host__ __device__ constexpr int split_xi(int N) { return (N == 128 || N == 160 || N == 256) ? 2 : 1; }
 template <int N, int V> struct SplitShape {
   static constexpr int N1 = split_n1(N, V);
   static constexpr bool ok = N1 > 0;
   static constexpr int N2 = ok ? N / N1 : 1;
-  static constexpr int SLAB_NT = N <= 128 ? 128 : 256;
+  static constexpr int XI = split_xi(N);
+  static constexpr int SLAB_NT = XI * (N <= 128 ? 128 : 256);
   static constexpr int TT = V == 2 ? 8 : ((V == 0 || (V == 3 && N2 <= 16)) && N % 4 == 0) ? 4 : 2;
   static constexpr int PENCIL_NT = N * TT <= 1024 ? N * TT : 1024;
 };
 
-// Pencil block order: runs of consecutive x3 tiles per XCD, so that the TT-column pieces of one
-// 128-byte row segment are fetched by blocks that share an L2.
+// Pencil block order: runs of consecutive x3 tiles per XCD, so that the pieces of one 128-byte
+// row segment are fetched by blocks that share an L2.
 constexpr int PENCIL_XCD_RUN = 128;
 
-template <typename T, int N, int N1, int NT>
-__global__ void __launch_bounds__(NT) k_slab_t(const LaunchList L) {
+template <typename T, int N, int V>
+__global__ void __launch_bounds__((SplitShape<N, V>::SLAB_NT)) k_slab_t(const LaunchList L) {
   extern __shared__ __align__(16) unsigned char smem[];
+  using SH = SplitShape<N, V>;
   const int e = find_entry(L, blockIdx.x);
-  slab_body<T, N, N1, NT>(L, e, blockIdx.x - L.tile_start[e], smem);
+  slab_body<T, N, SH::N1, SH::SLAB_NT, SH::XI>(L, e, blockIdx.x - L.tile_start[e], smem);
 }
 
 template <typename T, int N, int V>
@@ -1093,16 +1165,17 @@ __global__ void __launch_bounds__((SplitShape<N, V>::PENCIL_NT)) k_pencil_t(cons
   using SH = SplitShape<N, V>;
   const int blk = xcd_block_chunked(blockIdx.x, gridDim.x, PENCIL_XCD_RUN);
   const int e = find_entry(L, blk);
-  pencil_body<T, N, SH::N2, SH::TT, SH::PENCIL_NT>(L, e, blk - L.tile_start[e], smem);
+  pencil_body<T, N, SH::N2, SH::TT, SH::PENCIL_NT, SH::XI>(L, e, blk - L.tile_start[e], smem);
 }
 
 template <int N, int V> void register_split(FftKernels &k) {
   if constexpr (SplitShape<N, V>::ok) {
     using SH = SplitShape<N, V>;
-    k.slab[V] = (const void *)k_slab_t<float, N, SH::N1, SH::SLAB_NT>;
+    k.slab[V] = (const void *)k_slab_t<float, N, V>;
     k.slab_nt[V] = SH::SLAB_NT;
-    k.slab_lds[V] = slab_lds_t<float, N, SH::N1>();
+    k.slab_lds[V] = slab_lds_t<float, N, SH::N1, SH::XI>();
     k.split_n1[V] = SH::N1;
+    k.split_xi[V] = SH::XI;
     k.pencil[V] = (const void *)k_pencil_t<float, N, V>;
     k.pencil_lds[V] = pencil_lds_t<float, N, SH::N2, SH::TT>();
     k.pencil_nt[V] = SH::PENCIL_NT;

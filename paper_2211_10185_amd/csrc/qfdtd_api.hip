@@ -189,9 +189,9 @@ int col_tiles(int N, int k, bool dbl) {
   const int tc = col_tile(dbl);
   return k * N * ((N + tc - 1) / tc);
 }
-// split-x2 schedule: slab tiles (x1 plane, fast x2 digit; a tile carries every state), pencil
-// tiles (state, slow x2 frequency, x3 column block)
-int slab_tiles(int N, int v) { return N * (N / g_fft[N].split_n1[v]); }
+// split-x2 schedule: slab tiles (group of split_xi x1 planes, fast x2 digit; a tile carries every
+// state), pencil tiles (state, slow x2 frequency, x3 column block)
+int slab_tiles(int N, int v) { return N / g_fft[N].split_xi[v] * (N / g_fft[N].split_n1[v]); }
 // At small N the slab tiles are few (N * N2, each taking all k states in turn), so up to this size
 // each state gets tiles of its own (aux 1), which reread the factor rows from cache.  Measured at
 // k = 3 on one stream: 42.7 -> 35.5 us per step at 96, 48.1 -> 45.4 at 108, but 60.0 -> 65.9 at
