@@ -102,7 +102,8 @@ SPLIT_CASES = [  # N, kinetic, potential, split variant
     (144, S.K_NR_SIN2, S.V_CORNELL, 3), (150, S.K_REL, S.V_HARMONIC, 3), (160, S.K_REL, S.V_CORNELL, 3),
     (162, S.K_NR_SIN2, S.V_CORNELL, 3), (180, S.K_NR_P2, S.V_CORNELL, 3), (192, S.K_REL, S.V_CORNELL, 3),
     (216, S.K_NR_SIN2, S.V_HARMONIC, 3), (240, S.K_REL, S.V_CORNELL, 3), (250, S.K_REL, S.V_CORNELL, 3),
-    (120, S.K_NR_SIN2, S.V_CORNELL, 3), (200, S.K_REL, S.V_CORNELL, 0), (200, S.K_NR_SIN2, S.V_HARMONIC, 3)]
+    (120, S.K_NR_SIN2, S.V_CORNELL, 3), (200, S.K_REL, S.V_CORNELL, 0), (200, S.K_NR_SIN2, S.V_HARMONIC, 3),
+    (128, S.K_NR_P2, S.V_HARMONIC, 1)]
 
 
 @pytest.mark.parametrize("N,kind,vkind,variant", SPLIT_CASES)
