@@ -5,7 +5,7 @@
 //  k_dt_tables    e^{-dt V/2}, e^{-dt V}, e^{-dt t(k_j)} for the current dt (FP64, stored
 //                 in the state precision)
 //  k_stencil      H_K^(0) step psi' = A psi + B dt/(2 M a^2) L psi            (Sec. 2, eq. HK0)
-//  k_parity       P^+, P^-, P^-_{p_k} by mirrored gathers                    (Sec. 3, Fig. 1 text)
+//  k_parity       P^+, P^-, P^-_{p_k} over reflection orbits                  (Sec. 3, Fig. 1 text)
 //  k_gram ...     FP64 Gram matrix, Cholesky, Psi <- Psi R^{-1}              (Sec. 1: orthogonal projection)
 //  k_energy_*     FP64 <psi|V|psi>, <psi|H_K|psi>, <psi|psi>                (Sec. 2, general solution)
 //
@@ -457,50 +457,63 @@ __device__ __forceinline__ int mirror(int i, int N, bool periodic) {
   return periodic ? (m == N ? 0 : m) : m;
 }
 
+// Each thread takes sites gi; a projected state is processed by reflection orbits: the site of
+// the orbit with the smallest index reads the orbit's values once and writes every member's
+// output (the other members' threads do nothing), so each value is read and written once.  A
+// member's output is the same expression of its own value and its own images as for a single
+// site, so results do not depend on the grouping.  P^+/P^-: orbit {x, R x} (R reflects all three
+// axes); P^-_{p_k}: {x, R_k x, R_o x, R x} (R_k reflects axis k, R_o the other two).
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) k_parity(const LaunchList L) {
   const int e = find_entry(L, blockIdx.x);
   const PassDesc &d = *(const PassDesc *)L.descp[e];
   const uint32_t mode = L.mode[e];
-  const int N = d.N;
-  const size_t N3 = (size_t)N * N * N;
-  const C<T> *src = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi);
-  C<T> *dst = (C<T> *)((mode & M_SWAP) ? d.psi : d.alt);
+  // site indices in 32 bits: k N^3 <= 8 * 512^3 = 2^30
+  const uint32_t N = (uint32_t)d.N;
+  const uint32_t N3 = N * N * N;
+  const C<T> *__restrict__ src = (const C<T> *)((mode & M_SWAP) ? d.alt : d.psi);
+  C<T> *__restrict__ dst = (C<T> *)((mode & M_SWAP) ? d.psi : d.alt);
   const bool periodic = d.kin != KIN_FDTD;
-  const long long base = (long long)(blockIdx.x - L.tile_start[e]) * RED_THREADS * EW_PER_THREAD;
-  const long long total = (long long)d.k * N3;
+  const uint32_t base = (uint32_t)(blockIdx.x - L.tile_start[e]) * RED_THREADS * EW_PER_THREAD;
+  const uint32_t total = (uint32_t)d.k * N3;
 #pragma unroll
   for (int q = 0; q < EW_PER_THREAD; ++q) {
-    const long long gi = base + q * RED_THREADS + threadIdx.x;
+    const uint32_t gi = base + q * RED_THREADS + threadIdx.x;
     if (gi >= total) break;
-    const int s = (int)(gi / N3);
-    const size_t x = (size_t)(gi - (long long)s * N3);
-    const C<T> *sp = src + (size_t)s * N3;
-    const int i3 = (int)(x % N), i2 = (int)((x / N) % N), i1 = (int)(x / ((size_t)N * N));
+    const uint32_t s = gi / N3;
+    const uint32_t x = gi - s * N3, sb = s * N3;
+    const uint32_t r = x / N, i3 = x - r * N, i1 = r / N, i2 = r - i1 * N;
     const int sec = d.sector[s];
-    const C<T> v = sp[x];
-    if (sec == 0) { dst[gi] = v; continue; }
-    const int m1 = mirror(i1, N, periodic), m2 = mirror(i2, N, periodic), m3 = mirror(i3, N, periodic);
-    auto at = [&](int j1, int j2, int j3) -> C<T> {
-      if (j1 == N || j2 == N || j3 == N) return mkc<T>(0, 0);
-      return sp[((size_t)j1 * N + j2) * N + j3];
-    };
-    const C<T> all = at(m1, m2, m3);
-    C<T> out;
-    if (sec == 1) out = cscale(cadd(v, all), (T)0.5);
-    else if (sec == 2) out = cscale(csub(v, all), (T)0.5);
-    else {
-      // P^-_{p_k} = (1 + R_other)(1 - R_k)/4
-      C<T> r_oth, r_k;
-      if (sec == 3) { r_oth = at(i1, m2, m3); r_k = at(m1, i2, i3); }
-      else if (sec == 4) { r_oth = at(m1, i2, m3); r_k = at(i1, m2, i3); }
-      else { r_oth = at(m1, m2, i3); r_k = at(i1, i2, m3); }
-      out = cscale(csub(cadd(v, r_oth), cadd(r_k, all)), (T)0.25);
-    }
+    if (sec == 0) { dst[gi] = src[gi]; continue; }
     // walled lattice: a site with some i_l = 0 mirrors onto the wall, so a state of definite
-    // parity vanishes there (the projector stays idempotent)
-    if (!periodic && (i1 == 0 || i2 == 0 || i3 == 0)) out = mkc<T>(0, 0);
-    dst[gi] = out;
+    // parity vanishes there (the projector stays idempotent); the other sites' images stay inside
+    if (!periodic && (i1 == 0 || i2 == 0 || i3 == 0)) { dst[gi] = mkc<T>(0, 0); continue; }
+    const uint32_t m1 = mirror(i1, N, periodic), m2 = mirror(i2, N, periodic), m3 = mirror(i3, N, periodic);
+    auto idx = [&](uint32_t j1, uint32_t j2, uint32_t j3) -> uint32_t { return sb + (j1 * N + j2) * N + j3; };
+    const uint32_t xa = idx(m1, m2, m3);
+    if (sec == 1 || sec == 2) {
+      if (xa < gi) continue;                     // the orbit's first site handles it
+      const C<T> v = src[gi], w = src[xa];
+      if (sec == 1) {
+        dst[gi] = cscale(cadd(v, w), (T)0.5);
+        if (xa != gi) dst[xa] = cscale(cadd(w, v), (T)0.5);
+      } else {
+        dst[gi] = cscale(csub(v, w), (T)0.5);
+        if (xa != gi) dst[xa] = cscale(csub(w, v), (T)0.5);
+      }
+      continue;
+    }
+    // P^-_{p_k} = (1 + R_o)(1 - R_k)/4; member z: (v(z) + v(R_o z)) - (v(R_k z) + v(R z))
+    uint32_t xk, xo;
+    if (sec == 3) { xk = idx(m1, i2, i3); xo = idx(i1, m2, m3); }
+    else if (sec == 4) { xk = idx(i1, m2, i3); xo = idx(m1, i2, m3); }
+    else { xk = idx(i1, i2, m3); xo = idx(m1, m2, i3); }
+    if (xk < gi || xo < gi || xa < gi) continue;
+    const C<T> a = src[gi], b = src[xk], c = src[xo], f = src[xa];
+    dst[gi] = cscale(csub(cadd(a, c), cadd(b, f)), (T)0.25);
+    if (xk != gi) dst[xk] = cscale(csub(cadd(b, f), cadd(a, c)), (T)0.25);
+    if (xo != gi && xo != xk) dst[xo] = cscale(csub(cadd(c, a), cadd(f, b)), (T)0.25);
+    if (xa != gi && xa != xk && xa != xo) dst[xa] = cscale(csub(cadd(f, b), cadd(c, a)), (T)0.25);
   }
 }
 
