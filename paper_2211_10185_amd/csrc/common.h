@@ -221,7 +221,7 @@ struct FftKernels {
   int plane_nt;
   // split-x2 two-pass schedule (slab and pencil passes, complex64), where instantiated, by
   // variant (x2 = N1 x N2 and the pencil tile width)
-  const void *slab[4];
+  const void *slab[4], *slab_edge[4];   // steady pass; chunk-edge and plain-transform passes
   size_t slab_lds[4];
   int slab_nt[4], split_n1[4], split_xi[4];
   const void *pencil[4];

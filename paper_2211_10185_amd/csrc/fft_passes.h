@@ -810,11 +810,12 @@ template <typename T, bool G = false> struct StateBuf {
 // the potential factor rows of the tile are read from HBM once for all k states (or, with the
 // entry's aux = 1, for one state per tile: k times the tiles, each reading the factor rows).  The
 // tile's LDS holds row a of the group's plane j as line j N1 + a.  Steady mode
-// (M_INV | M_MID | M_FWD): A^-1 from HBM, inverse x3, x h^2 (fused with the last inverse and
-// first forward stages), forward x3, A to HBM.  Other modes: chunk start (M_PRE | M_FWD: x h,
+// (M_INV | M_MID | M_FWD, EDGE false): A^-1 from HBM, inverse x3, x h^2 (fused with the last
+// inverse and first forward stages), forward x3, A to HBM.  The other modes (EDGE true, a kernel of
+// its own so that its registers do not weigh on the steady pass): chunk start (M_PRE | M_FWD: x h,
 // forward x3, A), chunk end (M_INV | M_POST: A^-1, inverse x3, x h) and plain transforms.  M_INV
 // reads the split order, M_FWD writes it; otherwise the state is read or written in natural order.
-template <typename T, int N, int N1, int NT, int XI>
+template <typename T, int N, int N1, int NT, int XI, bool EDGE>
 __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, unsigned char *smem) {
   constexpr int N2 = N / N1;
   constexpr int P = padded_len(N);
@@ -899,6 +900,8 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
       }
     }
   };
+  if constexpr (!EDGE) {
+  // every mode; the steady one fused (the API sends the other modes to the EDGE kernel)
   if (mode == (M_INV | M_MID | M_FWD)) {
     constexpr int RM = PL.r[M];
     using SS = SG<Rows, N, RM, NT>;
@@ -982,6 +985,94 @@ __device__ __forceinline__ void slab_body(const LaunchList &L, int e, int t, uns
         g[site(pl, a, n)] = buf[Rows::at(bl, n)];
       }
     }
+  }
+  } else {
+  // Natural-order tile accesses (chunk edges, plain transforms): each thread takes elements
+  // threadIdx.x + it NT, UB at a time, with all UB global loads issued before they are used.
+  constexpr int NE = NR * N;
+  constexpr int EPT = (NE + NT - 1) / NT;
+  constexpr int UB = EPT < 8 ? EPT : 8;
+  // state rows (times the factor f if given) to the LDS lines
+  auto natural_to_lds = [&](const C<T> *g, const void *f) {
+    const StateBuf<T, true> sb(g);
+#pragma unroll 1
+    for (int it0 = 0; it0 < EPT; it0 += UB) {
+      C<T> v[UB], h[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int idx = (int)threadIdx.x + (it0 + u) * NT;
+        if (it0 + u < EPT && (NE % NT == 0 || idx < NE)) {
+          const int bl = idx / N, n = idx - bl * N, pl = bl / N1, a = bl - pl * N1;
+          v[u] = sb.load((uint32_t)(site(pl, a, n) * sizeof(C<T>)), 0);
+          if (f) h[u] = fac(f, site(pl, a, n));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int idx = (int)threadIdx.x + (it0 + u) * NT;
+        if (it0 + u < EPT && (NE % NT == 0 || idx < NE)) {
+          const int bl = idx / N, n = idx - bl * N;
+          C<T> x = v[u];
+          if (f) x = vc ? cmul(x, h[u]) : cscale(x, h[u].x);
+          buf[Rows::at(bl, n)] = x;
+        }
+      }
+    }
+  };
+  // LDS lines (times the factor f if given) to the state rows
+  auto lds_to_natural = [&](C<T> *g, const void *f) {
+    const StateBuf<T, true> sb(g);
+#pragma unroll 1
+    for (int it0 = 0; it0 < EPT; it0 += UB) {
+      C<T> h[UB];
+      if (f) {
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int idx = (int)threadIdx.x + (it0 + u) * NT;
+          if (it0 + u < EPT && (NE % NT == 0 || idx < NE)) {
+            const int bl = idx / N, n = idx - bl * N, pl = bl / N1, a = bl - pl * N1;
+            h[u] = fac(f, site(pl, a, n));
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int idx = (int)threadIdx.x + (it0 + u) * NT;
+        if (it0 + u < EPT && (NE % NT == 0 || idx < NE)) {
+          const int bl = idx / N, n = idx - bl * N, pl = bl / N1, a = bl - pl * N1;
+          C<T> x = buf[Rows::at(bl, n)];
+          if (f) x = vc ? cmul(x, h[u]) : cscale(x, h[u].x);
+          sb.store(x, (uint32_t)(site(pl, a, n) * sizeof(C<T>)), 0);
+        }
+      }
+    }
+  };
+  const void *fmid = (mode & M_MID) ? d.h2fac : (mode & M_POST) ? d.hfac : nullptr;
+  for (int s = s0; s < s1; ++s) {
+    C<T> *g = (C<T> *)d.psi + (size_t)s * N3 + voff;
+    __syncthreads();       // the twiddle tables; the previous state's reads of the LDS rows
+    if (mode & M_INV) a_inverse_to_lds(g);
+    else natural_to_lds(g, (mode & M_PRE) ? d.hfac : nullptr);
+    __syncthreads();
+    if (mode & M_INV) fft_lines_t<T, N, true, Rows, NT>(buf, tw);
+    if (mode & M_FWD) {
+      if (fmid) {
+        for (int idx = threadIdx.x; idx < NE; idx += NT) {
+          const int bl = idx / N, n = idx - bl * N;
+          const int pl = bl / N1, a = bl - pl * N1;
+          const C<T> h = fac(fmid, site(pl, a, n));
+          const int o = Rows::at(bl, n);
+          buf[o] = vc ? cmul(buf[o], h) : cscale(buf[o], h.x);
+        }
+        __syncthreads();
+      }
+      fft_lines_t<T, N, false, Rows, NT>(buf, tw);
+      a_forward_from_lds(g);
+    } else {
+      // the factor of the chunk end (or a middle factor) is applied on the way out
+      lds_to_natural(g, fmid);
+    }
+  }
   }
 }
 
@@ -1156,7 +1247,14 @@ __global__ void __launch_bounds__((SplitShape<N, V>::SLAB_NT)) k_slab_t(const La
   extern __shared__ __align__(16) unsigned char smem[];
   using SH = SplitShape<N, V>;
   const int e = find_entry(L, blockIdx.x);
-  slab_body<T, N, SH::N1, SH::SLAB_NT, SH::XI>(L, e, blockIdx.x - L.tile_start[e], smem);
+  slab_body<T, N, SH::N1, SH::SLAB_NT, SH::XI, false>(L, e, blockIdx.x - L.tile_start[e], smem);
+}
+template <typename T, int N, int V>
+__global__ void __launch_bounds__((SplitShape<N, V>::SLAB_NT)) k_slab_edge_t(const LaunchList L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using SH = SplitShape<N, V>;
+  const int e = find_entry(L, blockIdx.x);
+  slab_body<T, N, SH::N1, SH::SLAB_NT, SH::XI, true>(L, e, blockIdx.x - L.tile_start[e], smem);
 }
 
 template <typename T, int N, int V>
@@ -1172,6 +1270,7 @@ template <int N, int V> void register_split(FftKernels &k) {
   if constexpr (SplitShape<N, V>::ok) {
     using SH = SplitShape<N, V>;
     k.slab[V] = (const void *)k_slab_t<float, N, V>;
+    k.slab_edge[V] = (const void *)k_slab_edge_t<float, N, V>;
     k.slab_nt[V] = SH::SLAB_NT;
     k.slab_lds[V] = slab_lds_t<float, N, SH::N1, SH::XI>();
     k.split_n1[V] = SH::N1;

@@ -139,9 +139,9 @@ hipError_t fft_table_init() {
     }
   for (int n = 0; n <= 256; ++n)
     for (int v = 0; v < 4; ++v) {
-      const void *fs[2] = {g_fft[n].slab[v], g_fft[n].pencil[v]};
-      const size_t ls[2] = {g_fft[n].slab_lds[v], g_fft[n].pencil_lds[v]};
-      for (int q = 0; q < 2; ++q)
+      const void *fs[3] = {g_fft[n].slab[v], g_fft[n].slab_edge[v], g_fft[n].pencil[v]};
+      const size_t ls[3] = {g_fft[n].slab_lds[v], g_fft[n].slab_lds[v], g_fft[n].pencil_lds[v]};
+      for (int q = 0; q < 3; ++q)
         if (fs[q]) {
           hipError_t e = hipFuncSetAttribute(fs[q], hipFuncAttributeMaxDynamicSharedMemorySize, (int)ls[q]);
           if (e != hipSuccess) return e;
@@ -336,8 +336,10 @@ struct Entry {
   int aux;
 };
 
+// F_SLAB: slab passes of any mode (split below into the steady kernel and F_SLAB_EDGE, the kernel
+// of the chunk-edge and plain-transform modes)
 enum Fam { F_PLANE, F_ROW, F_COL, F_STENCIL, F_STENCIL2, F_PARITY, F_TO64, F_GRAM, F_APPLY, F_EPART, F_KPART, F_GFIN, F_EFIN,
-           F_SLAB, F_PENCIL };
+           F_SLAB, F_PENCIL, F_SLAB_EDGE };
 
 // Algorithmic bytes moved by one member's share of a launch (for timing): every state is read
 // and written once, and the per-site potential factor, which all k states of the member share,
@@ -354,6 +356,7 @@ double entry_bytes(const Entry &e, Fam f) {
     case F_PLANE:
     case F_ROW:
     case F_SLAB:
+    case F_SLAB_EDGE:
       // A/B combine: read alt and psi and V, write psi (and alt when the forward follows)
       if (e.mode & M_COMB) return n * (3 * s + ((e.mode & M_FWD) ? s : 0.0)) + n3 * fsz;
       return n * 2 * s + ((e.mode & (M_PRE | M_MID | M_POST)) ? n3 * fsz : 0.0);
@@ -402,6 +405,16 @@ qfdtd_status run_fft_family(Fam f, std::vector<Entry> &es, bool dbl, hipStream_t
 
 qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStream_t sto) {
   if (es.empty()) return QFDTD_OK;
+  if (f == F_SLAB) {
+    // steady slab passes and the other modes run in separate kernels
+    const uint32_t steady = M_INV | M_MID | M_FWD;
+    std::vector<Entry> st_es, ed_es;
+    for (auto &e : es) (e.mode == steady ? st_es : ed_es).push_back(e);
+    if (!ed_es.empty()) {
+      if (!st_es.empty()) QF_TRY(run_family(F_SLAB, st_es, dbl, KS, sto));
+      return run_family(F_SLAB_EDGE, ed_es, dbl, KS, sto);
+    }
+  }
   if ((f == F_PLANE || f == F_ROW || f == F_COL) && KS >= 0) return run_fft_family(f, es, dbl, sto);
   const int grp = KS <= -2 ? -2 - KS : -1;   // multi-size kernel of this group
   qfdtd_ctx *c0 = es[0].c;
@@ -425,7 +438,7 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
       if (f == F_PLANE) l = K.plane_lds[dbl];
       else if (f == F_ROW) l = K.row_lds[dbl];
       else if (f == F_COL) l = K.col_lds[dbl];
-      else if (f == F_SLAB) l = K.slab_lds[e.c->split_v];
+      else if (f == F_SLAB || f == F_SLAB_EDGE) l = K.slab_lds[e.c->split_v];
       else if (f == F_PENCIL) l = K.pencil_lds[e.c->split_v];
       if (l > lds) lds = l;
       if (grp >= 0 && (f == F_PLANE || f == F_ROW || f == F_COL))
@@ -442,7 +455,7 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
     if (f == F_PLANE || f == F_ROW || f == F_COL)
       cls = meas_copy ? TC_MEAS : (f == F_PLANE ? TC_PLANE : f == F_ROW ? TC_ROW : TC_COL);
     else if (f == F_STENCIL || f == F_STENCIL2) cls = TC_STENCIL;
-    else if (f == F_SLAB) cls = TC_SLAB;
+    else if (f == F_SLAB || f == F_SLAB_EDGE) cls = TC_SLAB;
     else if (f == F_PENCIL) cls = TC_PENCIL;
     const int tix = cls >= 0 ? tbegin(c0, cls, bytes, st) : -1;
     const FftKernels &K = g_fft[es[base].c->N];
@@ -464,6 +477,7 @@ qfdtd_status run_family(Fam f, std::vector<Entry> &es, bool dbl, int KS, hipStre
       case F_ROW: go(frow, LINE_THREADS, lds); break;
       case F_COL: go(fcol, LINE_THREADS, lds); break;
       case F_SLAB: go(K.slab[c0->split_v], K.slab_nt[c0->split_v], lds); break;
+      case F_SLAB_EDGE: go(K.slab_edge[c0->split_v], K.slab_nt[c0->split_v], lds); break;
       case F_PENCIL: go(K.pencil[c0->split_v], K.pencil_nt[c0->split_v], lds); break;
       case F_STENCIL: go(stencil_kernel(dbl), RED_THREADS, 0); break;
       case F_STENCIL2: go(stencil2_kernel(), S2_THREADS, 0); break;
