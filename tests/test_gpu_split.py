@@ -171,3 +171,34 @@ def test_split_schedule_state_groups_with_parity_sectors_match_oracle(groups):
     print("energy err", np.max(energy_errors(E, ref["energies"])), flush=True)
     assert np.max(energy_errors(E, ref["energies"])) < 1e-5, (E, ref["energies"])
     assert np.max(wavefunction_errors(psi, ref["states"], ref["energies"])) < 1e-4
+
+
+def test_batch_mixing_steady_and_chunk_edge_slab_passes_is_bitwise_alone():
+    # two split members of one size with chunks of 4 and 6 steps: some slab launches hold one
+    # member's chunk-end pass beside the other's steady pass (the two run as separate kernels);
+    # a member of another split size rides along
+    from paper_2211_10185_amd.solver import batch_evolve
+    probs = [S.Problem(N=128, a=0.05, m=1.5, kinetic=S.K_REL, vkind=S.V_CORNELL, vparams=(0.3, 0.2, 0.025),
+                       k=2, precision=S.PREC_C64, dt=0.05 / 8, steps=10, measure_every=4, seed=21),
+             S.Problem(N=128, a=8.0 / 128, m=1.0, kinetic=S.K_NR_SIN2, vkind=S.V_HARMONIC, vparams=(1.0,),
+                       k=1, precision=S.PREC_C64, dt=0.01, steps=13, measure_every=6, seed=22),
+             S.Problem(N=160, a=8.0 / 160, m=1.0, kinetic=S.K_NR_P2, vkind=S.V_HARMONIC, vparams=(1.0,),
+                       k=3, precision=S.PREC_C64, dt=0.01, steps=7, measure_every=5, seed=23)]
+    print("batch of split members, chunks of 4, 6 and 5 steps", flush=True)
+    alone = []
+    for p in probs:
+        s = solver(p, split=True)
+        assert s.schedule["split"]
+        s.set_states(p.init_states())
+        s.evolve(p.steps, p.dt)
+        alone.append(s.states())
+        s.close()
+    ss = [solver(p, split=True) for p in probs]
+    for s, p in zip(ss, probs):
+        s.set_states(p.init_states())
+    batch_evolve(ss, [p.steps for p in probs], [p.dt for p in probs])
+    for s, (Ea, psia) in zip(ss, alone):
+        Eb, psib = s.states()
+        s.close()
+        assert np.array_equal(Ea, Eb)
+        assert np.array_equal(psia, psib)
